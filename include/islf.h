@@ -1,0 +1,234 @@
+/*
+ * islf — MI355X (gfx950) checkerboard Metropolis engine for the thin-film
+ * nearest-neighbour Ising model of Block, Kim, Virnau and Binder,
+ * "Anisotropic interfacial tension, contact angles, and line tensions: a
+ * GPU-based Monte Carlo study of the Ising model" (arXiv:1411.5588).
+ *
+ * Plain C ABI: plain pointers and sizes, no C++ or framework types.  Every
+ * entry point returns an islf_status; nothing throws across the boundary.
+ * On failure islf_last_error() returns a thread-local message that stays valid
+ * until the next call on the same thread.  Calls on one context are not
+ * thread-safe; separate contexts are independent.
+ *
+ * Model (Sec. II.A, Eq. 1):
+ *   E = -J sum_<ij> eps_ij S_i S_j - H sum_i S_i - h1 sum_{x=0} S_i - hn sum_{x=Lx-1} S_i
+ * on an Lx x Ly x Lz simple-cubic film, S = +-1, periodic in z, free surfaces
+ * at x = 0 (the paper's layer k_x = 1) and x = Lx-1 (layer k_x = n).  The y
+ * boundary is periodic, antiperiodic, or the generalized antiperiodic
+ * condition of Sec. II.A Eq. 11, S(k_x, k_y +- Ly, k_z) = -S(Lx+1-k_x, k_y, k_z):
+ * the y-seam bond of site (x, Ly-1, z) joins (Lx-1-x, 0, z) with eps = -1.
+ * Each site owns three forward bond slots (x+1 inside the film, z+1 mod Lz,
+ * y+1 or the seam); a pair joined by two slots (Ly = 2 or Lz = 2) counts twice.
+ *
+ * Dynamics (Appendix: checkerboard update): one sweep runs four phases,
+ * phase(x,y,z) = 2*[y == 0] + ((x+y+z) & 1), in the order 0,1,2,3; no bond
+ * joins two sites of one phase under any of the three y boundaries, so every
+ * site of a phase may be updated at once.  A site flips iff u < thr, where
+ * u is a uint32 word of Philox4x32-10 (key = (seed mod 2^32, seed >> 32),
+ * counter = (g, t, replica, 0), g = (((x*Ly+y)*ceil(Lz/8) + (z>>3)) << 1) | (z&1),
+ * word (z>>1)&3, t = the replica's own sweep index) and
+ * thr = 2^32 if dE <= 0 else floor(2^32 exp(-beta dE)), dE = 2 s (J n + h_site)
+ * evaluated in IEEE double on the host once per parameter set.  A random
+ * initial state uses counter (g, 0, replica, 1): spin +1 iff the top bit is 0.
+ * Results are therefore a deterministic function of the inputs: the same
+ * spins and observables for every execution form, tile shape and batch mix.
+ *
+ * Observables (Eq. 7 and the Eq. 19 integrand), one record per sweep:
+ *   B  = sum over slots eps S_i S_j,  M = sum S,  M1 = sum_{x=0} S,  Mn = sum_{x=Lx-1} S.
+ *
+ * Host spin layout for set/get: int8 +-1 at s[(x*Ly + y)*Lz + z].
+ */
+#ifndef ISLF_H
+#define ISLF_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    ISLF_OK = 0,
+    ISLF_EINVAL = 1,   /* invalid argument or shape                          */
+    ISLF_ENOMEM = 2,   /* device or host allocation failed                   */
+    ISLF_EDEVICE = 3,  /* a HIP call failed                                  */
+    ISLF_ESTATE = 4,   /* call not valid in the context's current state      */
+    ISLF_ERANGE = 5    /* index out of range (Philox group, sweep, record)   */
+} islf_status;
+
+typedef enum { ISLF_YBC_PBC = 0, ISLF_YBC_APBC = 1, ISLF_YBC_GAPBC = 2 } islf_ybc;
+typedef enum { ISLF_SPIN_INT8 = 0, ISLF_SPIN_BITPACK = 1 } islf_spin_format;
+typedef enum { ISLF_INIT_RANDOM = 0, ISLF_INIT_UP = 1, ISLF_INIT_DOWN = 2, ISLF_INIT_HOST = 3 } islf_init;
+
+/* How islf_sweep issues work.  All forms give bit-identical results.
+ *  PLAIN      : one launch per replica per phase (one lattice per launch).
+ *  BATCHED    : one launch per phase covering every replica.
+ *  PERSISTENT : one launch for all requested sweeps of every replica; the
+ *               phases are separated by device-side barriers. */
+typedef enum { ISLF_EXEC_PLAIN = 0, ISLF_EXEC_BATCHED = 1, ISLF_EXEC_PERSISTENT = 2 } islf_exec;
+
+/* One replica (Sec. II.A Eq. 1 parameters plus the Markov-chain identity).
+ * Lx >= 1, Ly >= 2, Lz >= 2 and even; beta in [0, +inf]; J, H, h1, hn finite.
+ * h1 acts on x = 0, hn on x = Lx-1 (a one-layer film feels both, H + h1 + hn).
+ * The paper's convention is hn = -h1 (Sec. II.A); any pair is accepted.  */
+typedef struct {
+    int32_t Lx, Ly, Lz;
+    int32_t ybc;          /* islf_ybc                                       */
+    double J, beta, H, h1, hn;
+    uint64_t seed;        /* Philox key                                     */
+    uint32_t replica;     /* enters the Philox counter; caller-chosen id    */
+    int32_t init;         /* islf_init                                      */
+} islf_replica_desc;
+
+/* Observables after one completed sweep (exact integers). */
+typedef struct {
+    int64_t B, M, M1, Mn;
+} islf_obs;
+
+typedef struct islf_ctx islf_ctx;
+
+/* Device allocator hooks (e.g. a framework's caching allocator).  alloc
+ * returns a device pointer aligned to at least 256 bytes, or NULL. */
+typedef void *(*islf_alloc_fn)(size_t bytes, void *user);
+typedef void (*islf_free_fn)(void *ptr, void *user);
+
+/* ---------------------------------------------------------------------- */
+/* Context                                                                 */
+/* ---------------------------------------------------------------------- */
+
+/* Creates a context holding n_reps replicas (n_reps >= 1) in the given spin
+ * format, each with a ring of obs_capacity (>= 3) per-sweep records, and
+ * initialises every replica per its init field (ISLF_INIT_HOST starts all-up
+ * until islf_set_spins is called).  hip_stream (hipStream_t, may be NULL for
+ * the default stream) is borrowed: all device work of this context is issued
+ * on it.  Device memory comes from alloc/free if given, else hipMalloc.  On
+ * failure nothing stays allocated and *out is NULL.
+ * Errors: EINVAL (shape, n_reps, capacity, format), ERANGE (lattice too large
+ * for the 32-bit Philox group counter), ENOMEM, EDEVICE. */
+islf_status islf_create(const islf_replica_desc *reps, int32_t n_reps, int32_t spin_format,
+                        uint32_t obs_capacity, void *hip_stream, islf_ctx **out);
+islf_status islf_create_with_allocator(const islf_replica_desc *reps, int32_t n_reps,
+                                       int32_t spin_format, uint32_t obs_capacity,
+                                       void *hip_stream, islf_alloc_fn alloc,
+                                       islf_free_fn free_fn, void *user, islf_ctx **out);
+
+/* Synchronises the context's stream and releases everything it owns. */
+islf_status islf_destroy(islf_ctx *ctx);
+
+/* Number of replica slots and whether slot `rep` holds a live replica. */
+islf_status islf_num_replicas(const islf_ctx *ctx, int32_t *n);
+
+/* Copies the replica's parameters as given at creation. */
+islf_status islf_get_desc(const islf_ctx *ctx, int32_t rep, islf_replica_desc *out);
+
+/* Host <-> device spins, int8 +-1 in the host layout above; n must equal
+ * Lx*Ly*Lz.  set_spins also recomputes the initial observables and may only
+ * be called before the replica's first sweep (else ESTATE).  Both synchronise.
+ * Errors: EINVAL (n, values other than +-1), ERANGE (rep), ESTATE. */
+islf_status islf_set_spins(islf_ctx *ctx, int32_t rep, const int8_t *host, size_t n);
+islf_status islf_get_spins(islf_ctx *ctx, int32_t rep, int8_t *host, size_t n);
+
+/* ---------------------------------------------------------------------- */
+/* Sweeps (Appendix: checkerboard update; Sec. II.A Eq. 1)                 */
+/* ---------------------------------------------------------------------- */
+
+/* Selects the execution form used by islf_sweep (islf_exec). */
+islf_status islf_set_exec(islf_ctx *ctx, int32_t exec_mode);
+
+/* Enqueues n_sweeps sweeps of every live replica on the context's stream and
+ * returns without waiting.  Per sweep the per-flip changes of (B, M, M1, Mn)
+ * are reduced inside the update kernels and one record is stored per replica.
+ * Errors: ERANGE if a replica's sweep index would pass 2^32-1, EDEVICE. */
+islf_status islf_sweep(islf_ctx *ctx, uint32_t n_sweeps);
+
+/* Sweep index of the replica = number of sweeps it has completed (synchronises). */
+islf_status islf_sweep_count(islf_ctx *ctx, int32_t rep, uint64_t *t);
+
+/* ---------------------------------------------------------------------- */
+/* Measurement (Eq. 7, Eq. 19 integrands)                                  */
+/* ---------------------------------------------------------------------- */
+
+/* Copies records of sweeps first .. first+count-1 (0-based sweep numbers) of
+ * one replica to host memory; synchronises.  The ring keeps the most recent
+ * obs_capacity-1 records: older or not yet run sweeps give ERANGE. */
+islf_status islf_measure(islf_ctx *ctx, int32_t rep, uint64_t first, uint32_t count, islf_obs *out);
+
+/* Recomputes (B, M, M1, Mn) of the replica's current spins from scratch on
+ * the device (a check of the fused per-sweep reductions); synchronises. */
+islf_status islf_recompute(islf_ctx *ctx, int32_t rep, islf_obs *out);
+
+/* Energies E = ((-J B - H M) - h1 M1) - hn Mn (Eq. 1, IEEE double, left to
+ * right) of records first .. first+count-1, computed on the device and copied
+ * to host out[count]; synchronises.  Errors as islf_measure. */
+islf_status islf_energy(islf_ctx *ctx, int32_t rep, uint64_t first, uint32_t count, double *out);
+
+/* Per-replica means over records first .. first+count-1 of every live
+ * replica, computed on the device as (double)(exact int64 sum) / (double)count:
+ * out[5*r + {0,1,2,3,4}] = mean {E, B, M, M1, Mn} (E by the islf_energy
+ * formula, then averaged in index order).  Host out of 5*n_reps doubles;
+ * synchronises.  Errors: ERANGE if a replica lacks a requested record. */
+islf_status islf_means(islf_ctx *ctx, uint64_t first, uint32_t count, double *out);
+
+/* ---------------------------------------------------------------------- */
+/* Thermodynamic integration over the surface field (Eq. 9, Eq. 22)        */
+/* ---------------------------------------------------------------------- */
+
+/* Cumulative trapezoid on the device in IEEE double, left to right:
+ *   g_r = norm * (c1 * m1[r] + cn * mn[r]),  out[0] = 0,
+ *   out[r] = out[r-1] + (0.5 * (h[r] - h[r-1])) * (g_{r-1} + g_r).
+ * (c1, cn) = (-1, -1) is the literal integrand of Eq. 9; (-1, +1) integrates
+ * the field-conjugate -<m1 - mn> along hn = -h1.  h, m1, mn, out are DEVICE
+ * pointers to n doubles (n >= 1); runs on hip_stream and returns without
+ * waiting.  Errors: EINVAL (n < 1, NULL). */
+islf_status islf_integrate(const double *h, const double *m1, const double *mn, int32_t n,
+                           double c1, double cn, double norm, double *out, void *hip_stream);
+
+/* ---------------------------------------------------------------------- */
+/* Batching and serving                                                    */
+/* ---------------------------------------------------------------------- */
+
+/* Device bytes one replica needs in a context (spins, ring, tables, work
+ * lists), for admission by memory footprint. */
+islf_status islf_footprint_bytes(const islf_replica_desc *desc, int32_t spin_format,
+                                 uint32_t obs_capacity, uint64_t *bytes);
+
+/* Admits a replica into a free slot (or a new one) of a running context and
+ * initialises it; the replica starts at sweep 0 whatever the others' sweep
+ * indices are, and its draws depend only on its own (seed, replica, t).
+ * Synchronises.  Errors: EINVAL, ERANGE, ENOMEM. */
+islf_status islf_batch_add(islf_ctx *ctx, const islf_replica_desc *desc, int32_t *slot);
+
+/* Retires a replica: its slot stops sweeping and its memory is released
+ * (or kept for reuse).  Synchronises.  Errors: ERANGE (slot not live). */
+islf_status islf_batch_retire(islf_ctx *ctx, int32_t slot);
+
+/* Records k_sweeps sweeps of the current batch (in the current execution
+ * form) as a HIP graph; islf_run_graph replays it n_replays times on the
+ * context's stream.  Admitting or retiring a replica invalidates the graph
+ * (run_graph then returns ESTATE until the next capture). */
+islf_status islf_graph_capture(islf_ctx *ctx, uint32_t k_sweeps);
+islf_status islf_run_graph(islf_ctx *ctx, uint32_t n_replays);
+
+/* ---------------------------------------------------------------------- */
+/* Tuning                                                                  */
+/* ---------------------------------------------------------------------- */
+
+/* Number of tile variants of the update kernels, and the variant in use for
+ * a replica.  Every variant computes the same result; they differ only in
+ * the thread-to-site mapping.  islf_set_tile changes one replica's variant
+ * (rebuilding work lists); islf_autotune times each variant on the live
+ * batch for `sweeps` sweeps per trial (restoring the spins afterwards, so
+ * results are unaffected) and keeps the fastest per size class. */
+islf_status islf_num_tiles(int32_t spin_format, int32_t *n);
+islf_status islf_get_tile(const islf_ctx *ctx, int32_t rep, int32_t *tile);
+islf_status islf_set_tile(islf_ctx *ctx, int32_t rep, int32_t tile);
+islf_status islf_autotune(islf_ctx *ctx, uint32_t sweeps);
+
+/* Thread-local message describing the last failure on this thread. */
+const char *islf_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* ISLF_H */

@@ -1,0 +1,976 @@
+// Host side of libislf: the C ABI declared in include/islf.h.
+//
+// Owns contexts (replica slots, device buffers, work lists), builds the
+// Metropolis threshold tables in IEEE double (Sec. II.A Eq. 1 energy change,
+// acceptance min(1, exp(-beta dE)) on a uint32 draw), and issues the kernels
+// of islf_kernels.hip in the plain, batched or persistent form, optionally as
+// a captured HIP graph.
+#include <math.h>
+#include <stdarg.h>
+#include <stdio.h>
+#include <string.h>
+
+#include <algorithm>
+#include <string>
+#include <vector>
+
+#include "islf_internal.h"
+
+namespace islf {
+hipError_t launch_phase(int fmt, const RepDesc *descs, const RepState *st, const Entry *work, long n,
+                        int phase, int grid, hipStream_t s);
+hipError_t launch_end_sweep(const RepDesc *descs, RepState *st, const int *reps, int n, hipStream_t s);
+const void *persistent_kernel(int fmt);
+hipError_t launch_persistent(int fmt, const RepDesc *descs, RepState *st, const Entry *wm, long nm,
+                             const Entry *ws, long ns, const int *reps, int nreps, uint32_t nsweeps,
+                             GridSync *sync, int grid, hipStream_t s);
+hipError_t launch_init(int fmt, const RepDesc *descs, int rep, int mode, const int8_t *host, hipStream_t s);
+hipError_t launch_export(const RepDesc *descs, int rep, int8_t *out, hipStream_t s);
+hipError_t launch_recompute(const RepDesc *descs, int rep, const int8_t *spins, unsigned long long *out,
+                            hipStream_t s);
+hipError_t launch_set_state(RepState *st, int rep, const unsigned long long *obs, uint32_t t, hipStream_t s);
+hipError_t launch_zero(unsigned long long *p, long n, hipStream_t s);
+hipError_t launch_energy(const islf_obs *rec, uint32_t cap, uint64_t first, uint32_t count, double J,
+                         double H, double h1, double hn, double *out, hipStream_t s);
+hipError_t launch_means(const RepDesc *descs, const int *reps, int n, uint64_t first, uint32_t count,
+                        double *out, hipStream_t s);
+hipError_t launch_integrate(const double *h, const double *m1, const double *mn, int n, double c1, double cn,
+                            double norm, double *out, hipStream_t s);
+}  // namespace islf
+
+using namespace islf;
+
+// ---------------------------------------------------------------------------
+// errors
+// ---------------------------------------------------------------------------
+static thread_local std::string g_err;
+
+static islf_status fail(islf_status st, const char *fmt, ...)
+{
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    g_err = buf;
+    return st;
+}
+
+#define HIP_TRY(expr)                                                                     \
+    do {                                                                                  \
+        hipError_t e_ = (expr);                                                           \
+        if (e_ != hipSuccess)                                                             \
+            return fail(ISLF_EDEVICE, "%s failed: %s", #expr, hipGetErrorString(e_));     \
+    } while (0)
+
+extern "C" const char *islf_last_error(void) { return g_err.c_str(); }
+
+// ---------------------------------------------------------------------------
+// tile variants
+//  int8: a workgroup owns tj chunks x ty rows (tj*ty <= 256 threads) and each
+//        thread marches through mx x planes; tj is the most even split of the
+//        row's chunks into pieces of at most tj_max.
+//  bit-packed: 2^lj words x 2^ly rows x 2^(8-lj-ly) planes, one word each.
+//  seam phases (row y = 0, both formats): 2^lj_seam chunks/words x the rest in x.
+// ---------------------------------------------------------------------------
+struct I8Tile {
+    int tj_max, mx;
+};
+static const I8Tile kI8Tiles[] = {
+    {16, 16}, {32, 16}, {64, 16}, {128, 16}, {256, 16}, {16, 8},  {32, 8},   {64, 8},
+    {16, 32}, {32, 32}, {64, 32}, {128, 32}, {16, 64}, {32, 64}, {64, 64}, {256, 64},
+};
+static const int kNumI8Tiles = (int)(sizeof(kI8Tiles) / sizeof(kI8Tiles[0]));
+
+struct TileShape {
+    int lj, ly;
+};
+static const TileShape kBpTiles[] = {
+    {4, 4}, {5, 3}, {3, 5}, {6, 2}, {4, 2}, {3, 3}, {2, 4}, {5, 2}, {2, 6}, {1, 5}, {0, 6}, {1, 7},
+};
+static const int kNumBpTiles = (int)(sizeof(kBpTiles) / sizeof(kBpTiles[0]));
+
+static int num_tiles_of(int fmt) { return fmt == ISLF_SPIN_INT8 ? kNumI8Tiles : kNumBpTiles; }
+
+static long ceil_div(long a, long b) { return (a + b - 1) / b; }
+
+struct I8Shape {
+    int tj, ty, mx;
+};
+static I8Shape i8_shape(const islf_replica_desc &d, int tile)
+{
+    const long C = (d.Lz + 7) / 8;
+    const I8Tile &t = kI8Tiles[tile];
+    const long pieces = ceil_div(C, t.tj_max);
+    I8Shape s;
+    s.tj = (int)ceil_div(C, pieces);
+    s.ty = (int)std::min<long>(kBlock / s.tj, std::max(1, d.Ly - 1));
+    s.mx = std::min(t.mx, d.Lx);
+    return s;
+}
+
+// fraction of thread-steps that touch a real chunk / word
+static double tile_efficiency(const islf_replica_desc &d, int fmt, int tile)
+{
+    const double ny = d.Ly - 1;
+    if (fmt == ISLF_SPIN_INT8) {
+        const long C = (d.Lz + 7) / 8;
+        const I8Shape s = i8_shape(d, tile);
+        const double entries = (double)ceil_div(d.Lx, s.mx) * ceil_div((long)ny, s.ty) * ceil_div(C, s.tj);
+        return (double)d.Lx * ny * C / (entries * kBlock * s.mx);
+    }
+    const long J = (d.Lz + 63) / 64;
+    const TileShape &s = kBpTiles[tile];
+    const long tj = 1l << s.lj, ty = 1l << s.ly, tx = 1l << (8 - s.lj - s.ly);
+    return (double)d.Lx * ny * J / ((double)ceil_div(d.Lx, tx) * tx * ceil_div((long)ny, ty) * ty * ceil_div(J, tj) * tj);
+}
+
+static int default_tile(const islf_replica_desc *d, int fmt)
+{
+    double best = -1.0;
+    int best_i = 0;
+    for (int i = 0; i < num_tiles_of(fmt); ++i) {
+        if (fmt == ISLF_SPIN_INT8 && kI8Tiles[i].mx != 16) continue;
+        const double eff = tile_efficiency(*d, fmt, i);
+        if (eff > best + 1e-9) {
+            best = eff;
+            best_i = i;
+        }
+    }
+    return best_i;
+}
+
+static int seam_lj(const islf_replica_desc &d, int fmt)
+{
+    const long J = fmt == ISLF_SPIN_INT8 ? (d.Lz + 7) / 8 : (d.Lz + 63) / 64;
+    double best = -1.0;
+    int best_lj = 0;
+    for (int lj = 0; lj <= 8; ++lj) {
+        const long tj = 1l << lj, tx = 1l << (8 - lj);
+        const double eff = (double)d.Lx * J / ((double)ceil_div(d.Lx, tx) * tx * ceil_div(J, tj) * tj);
+        if (eff > best + 1e-9) {
+            best = eff;
+            best_lj = lj;
+        }
+    }
+    return best_lj;
+}
+
+// ---------------------------------------------------------------------------
+// context
+// ---------------------------------------------------------------------------
+struct Replica {
+    islf_replica_desc desc{};
+    bool live = false;
+    void *mem = nullptr;     // spins | records | accumulators
+    size_t mem_bytes = 0;
+    uint64_t t_host = 0;     // sweeps issued so far
+    int tile = 0;
+    RepDesc d{};
+    std::vector<Entry> main, seam;
+};
+
+struct islf_ctx {
+    int fmt = 0;
+    uint32_t cap = 0;
+    hipStream_t stream = nullptr;
+    islf_alloc_fn alloc = nullptr;
+    islf_free_fn free_fn = nullptr;
+    void *user = nullptr;
+    int exec = ISLF_EXEC_BATCHED;
+    int num_cu = 0;
+    int max_grid = 0;          // blocks of the phase kernels
+    int persistent_grid = 0;   // co-resident blocks of the persistent kernel
+
+    std::vector<Replica> reps;
+    int slot_capacity = 0;
+    RepDesc *d_desc = nullptr;
+    RepState *d_state = nullptr;
+    GridSync *d_sync = nullptr;
+    unsigned long long *d_scratch = nullptr;   // 64 x u64
+    int *d_live = nullptr;                      // live replica ids
+    int live_capacity = 0;
+    Entry *d_main = nullptr, *d_seam = nullptr;
+    long main_cap = 0, seam_cap = 0;
+    std::vector<long> main_off, main_len, seam_off, seam_len;  // per slot, within the device lists
+    long n_main = 0, n_seam = 0;
+    std::vector<int> live;
+    bool dirty = true;
+
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t graph_exec = nullptr;
+    uint32_t graph_sweeps = 0;
+    bool graph_valid = false;
+};
+
+static void *dev_alloc(islf_ctx *c, size_t bytes)
+{
+    if (bytes == 0) bytes = 256;
+    if (c->alloc) return c->alloc(bytes, c->user);
+    void *p = nullptr;
+    if (hipMalloc(&p, bytes) != hipSuccess) return nullptr;
+    return p;
+}
+
+static void dev_free(islf_ctx *c, void *p)
+{
+    if (!p) return;
+    if (c->free_fn) c->free_fn(p, c->user);
+    else (void)hipFree(p);
+}
+
+// ---------------------------------------------------------------------------
+// validation, sizes, thresholds
+// ---------------------------------------------------------------------------
+static islf_status validate(const islf_replica_desc *d)
+{
+    if (!d) return fail(ISLF_EINVAL, "NULL replica descriptor");
+    if (d->Lx < 1 || d->Ly < 2 || d->Lz < 2 || (d->Lz & 1))
+        return fail(ISLF_EINVAL, "invalid shape %dx%dx%d (need Lx>=1, Ly>=2, Lz>=2 even)", d->Lx, d->Ly, d->Lz);
+    if (d->ybc < 0 || d->ybc > 2) return fail(ISLF_EINVAL, "invalid y boundary %d", d->ybc);
+    if (d->init < 0 || d->init > 3) return fail(ISLF_EINVAL, "invalid init mode %d", d->init);
+    if (!(d->beta >= 0.0)) return fail(ISLF_EINVAL, "beta must be >= 0 (got %g)", d->beta);
+    if (!isfinite(d->J) || !isfinite(d->H) || !isfinite(d->h1) || !isfinite(d->hn))
+        return fail(ISLF_EINVAL, "J, H, h1, hn must be finite");
+    const unsigned long long rows = (unsigned long long)d->Lx * (unsigned long long)d->Ly;
+    const unsigned long long chunks = rows * (unsigned long long)((d->Lz + 7) / 8);
+    if (chunks * 2ull > (1ull << 32))
+        return fail(ISLF_ERANGE, "lattice %dx%dx%d exceeds the 32-bit Philox group counter", d->Lx, d->Ly, d->Lz);
+    if (chunks * 8ull >= (1ull << 32))
+        return fail(ISLF_ERANGE, "lattice %dx%dx%d exceeds 4 GiB of int8 spins", d->Lx, d->Ly, d->Lz);
+    return ISLF_OK;
+}
+
+static size_t spin_bytes(const islf_replica_desc *d, int fmt)
+{
+    const size_t rows = (size_t)d->Lx * d->Ly;
+    if (fmt == ISLF_SPIN_INT8) return rows * 8 * (size_t)((d->Lz + 7) / 8);
+    return rows * 2 * 4 * (size_t)((d->Lz + 63) / 64);
+}
+
+static size_t round_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
+
+static size_t replica_bytes(const islf_replica_desc *d, int fmt, uint32_t cap)
+{
+    return round_up(spin_bytes(d, fmt), 256) + round_up((size_t)cap * sizeof(islf_obs), 256) +
+           2 * kAccSlots * 4 * sizeof(long long);
+}
+
+// thr = 2^32 if dE <= 0 else floor(2^32 exp(-beta dE)), with
+// dE = 2 s (J n + h), n = 2*cnt - k, h the field of the site's layer.
+// Alongside: thr - 1 as 32 bits, the packed change (dB, dM) = (-2 s n, -2 s)
+// of a flip as dB + 65536 dM, and the set of moves that can never be taken.
+static void build_tables(const islf_replica_desc *d, RepDesc &D)
+{
+    uint64_t *thr = D.thr;
+    D.never_mask = 0;
+    for (int c = 0; c < kClasses; ++c) {
+        double h = d->H;
+        if (c & 1) h = h + d->h1;
+        if (c & 2) h = h + d->hn;
+        const int k = 6 - ((c & 1) ? 1 : 0) - ((c & 2) ? 1 : 0);
+        for (int u = 0; u < 2; ++u) {
+            const int s = 2 * u - 1;
+            for (int cnt = 0; cnt < 8; ++cnt) {
+                uint64_t v = 0;
+                int32_t dp = 0;
+                const int i = c * kThrPerClass + u * 8 + cnt;
+                if (cnt <= k) {
+                    const int n = 2 * cnt - k;
+                    const double dE = 2.0 * (double)s * (d->J * (double)n + h);
+                    if (dE <= 0.0) v = 1ull << 32;
+                    else v = (uint64_t)floor(ldexp(exp(-(d->beta * dE)), 32));
+                    dp = (-2 * s * n) + 65536 * (-2 * s);
+                    if (v == 0) D.never_mask |= 1ull << i;
+                }
+                thr[i] = v;
+                D.thr_m1[i] = v ? (uint32_t)(v - 1) : 0u;
+                D.dpack[i] = dp;
+            }
+        }
+    }
+}
+
+static void build_work(Replica &R, int rep_id, int fmt)
+{
+    const islf_replica_desc &d = R.desc;
+    R.main.clear();
+    R.seam.clear();
+    const int J = fmt == ISLF_SPIN_INT8 ? (d.Lz + 7) / 8 : (d.Lz + 63) / 64;
+    if (fmt == ISLF_SPIN_INT8) {
+        const I8Shape s = i8_shape(d, R.tile);
+        for (int x0 = 0; x0 < d.Lx; x0 += s.mx)
+            for (int y0 = 1; y0 < d.Ly; y0 += s.ty)
+                for (int j0 = 0; j0 < J; j0 += s.tj) R.main.push_back(Entry{rep_id, x0, y0, j0});
+        R.d.i8_tj = s.tj;
+        R.d.i8_ty = s.ty;
+        R.d.i8_mx = s.mx;
+        R.d.tile_lj = 0;
+        R.d.tile_ly = 0;
+    } else {
+        const TileShape &s = kBpTiles[R.tile];
+        const int tj = 1 << s.lj, ty = 1 << s.ly, tx = 1 << (8 - s.lj - s.ly);
+        for (int x0 = 0; x0 < d.Lx; x0 += tx)
+            for (int y0 = 1; y0 < d.Ly; y0 += ty)
+                for (int j0 = 0; j0 < J; j0 += tj) R.main.push_back(Entry{rep_id, x0, y0, j0});
+        R.d.tile_lj = s.lj;
+        R.d.tile_ly = s.ly;
+        R.d.i8_tj = R.d.i8_ty = R.d.i8_mx = 1;
+    }
+    const int lj = seam_lj(d, fmt);
+    const int tjs = 1 << lj, txs = 1 << (8 - lj);
+    for (int x0 = 0; x0 < d.Lx; x0 += txs)
+        for (int j0 = 0; j0 < J; j0 += tjs) R.seam.push_back(Entry{rep_id, x0, 0, j0});
+    R.d.tile_lj_seam = lj;
+}
+
+static void fill_desc(Replica &R, int fmt, uint32_t cap)
+{
+    const islf_replica_desc &d = R.desc;
+    RepDesc &D = R.d;
+    uint8_t *m = (uint8_t *)R.mem;
+    D.spins = m;
+    const size_t sb = round_up(spin_bytes(&d, fmt), 256);
+    D.rec = (islf_obs *)(m + sb);
+    D.acc = (long long *)(m + sb + round_up((size_t)cap * sizeof(islf_obs), 256));
+    build_tables(&d, D);
+    D.Lx = d.Lx; D.Ly = d.Ly; D.Lz = d.Lz;
+    D.C = (d.Lz + 7) / 8;
+    D.Lzp = 8 * D.C;
+    D.Wq = (d.Lz + 63) / 64;
+    D.seam_reflect = d.ybc == ISLF_YBC_GAPBC;
+    D.seam_invert = d.ybc != ISLF_YBC_PBC;
+    D.key0 = (uint32_t)(d.seed & 0xFFFFFFFFull);
+    D.key1 = (uint32_t)(d.seed >> 32);
+    D.replica = d.replica;
+    D.cap = cap;
+    D.fmt = fmt;
+    D.J = d.J; D.H = d.H; D.h1 = d.h1; D.hn = d.hn;
+}
+
+// ---------------------------------------------------------------------------
+// device-side tables
+// ---------------------------------------------------------------------------
+static islf_status ensure_slots(islf_ctx *c, int n)
+{
+    if (n <= c->slot_capacity) return ISLF_OK;
+    int cap = std::max(n, std::max(16, 2 * c->slot_capacity));
+    RepDesc *nd = (RepDesc *)dev_alloc(c, sizeof(RepDesc) * cap);
+    RepState *ns = (RepState *)dev_alloc(c, sizeof(RepState) * cap);
+    if (!nd || !ns) {
+        dev_free(c, nd);
+        dev_free(c, ns);
+        return fail(ISLF_ENOMEM, "cannot allocate replica tables for %d slots", cap);
+    }
+    HIP_TRY(launch_zero((unsigned long long *)ns, (long)(sizeof(RepState) * cap / 8), c->stream));
+    if (c->d_state) {
+        HIP_TRY(hipMemcpyAsync(ns, c->d_state, sizeof(RepState) * c->slot_capacity, hipMemcpyDeviceToDevice,
+                               c->stream));
+        HIP_TRY(hipMemcpyAsync(nd, c->d_desc, sizeof(RepDesc) * c->slot_capacity, hipMemcpyDeviceToDevice,
+                               c->stream));
+        HIP_TRY(hipStreamSynchronize(c->stream));
+    }
+    dev_free(c, c->d_desc);
+    dev_free(c, c->d_state);
+    c->d_desc = nd;
+    c->d_state = ns;
+    c->slot_capacity = cap;
+    c->graph_valid = false;
+    return ISLF_OK;
+}
+
+// Rebuilds the concatenated work lists and the live list after a change of
+// membership or tiles.
+static islf_status sync_tables(islf_ctx *c)
+{
+    if (!c->dirty) return ISLF_OK;
+    c->live.clear();
+    std::vector<Entry> M, S;
+    const int n = (int)c->reps.size();
+    c->main_off.assign(n, 0); c->main_len.assign(n, 0);
+    c->seam_off.assign(n, 0); c->seam_len.assign(n, 0);
+    for (int i = 0; i < n; ++i) {
+        Replica &R = c->reps[i];
+        if (!R.live) continue;
+        c->live.push_back(i);
+        c->main_off[i] = (long)M.size();
+        c->main_len[i] = (long)R.main.size();
+        M.insert(M.end(), R.main.begin(), R.main.end());
+        c->seam_off[i] = (long)S.size();
+        c->seam_len[i] = (long)R.seam.size();
+        S.insert(S.end(), R.seam.begin(), R.seam.end());
+    }
+    if ((long)M.size() > c->main_cap) {
+        dev_free(c, c->d_main);
+        c->main_cap = std::max<long>((long)M.size(), 2 * c->main_cap);
+        c->d_main = (Entry *)dev_alloc(c, sizeof(Entry) * c->main_cap);
+        if (!c->d_main) return fail(ISLF_ENOMEM, "cannot allocate work list");
+    }
+    if ((long)S.size() > c->seam_cap) {
+        dev_free(c, c->d_seam);
+        c->seam_cap = std::max<long>((long)S.size(), 2 * c->seam_cap);
+        c->d_seam = (Entry *)dev_alloc(c, sizeof(Entry) * c->seam_cap);
+        if (!c->d_seam) return fail(ISLF_ENOMEM, "cannot allocate work list");
+    }
+    if ((int)c->live.size() > c->live_capacity) {
+        dev_free(c, c->d_live);
+        c->live_capacity = std::max<int>((int)c->live.size(), 2 * c->live_capacity);
+        c->d_live = (int *)dev_alloc(c, sizeof(int) * c->live_capacity);
+        if (!c->d_live) return fail(ISLF_ENOMEM, "cannot allocate live list");
+    }
+    if (!M.empty()) HIP_TRY(hipMemcpyAsync(c->d_main, M.data(), sizeof(Entry) * M.size(), hipMemcpyHostToDevice, c->stream));
+    if (!S.empty()) HIP_TRY(hipMemcpyAsync(c->d_seam, S.data(), sizeof(Entry) * S.size(), hipMemcpyHostToDevice, c->stream));
+    if (!c->live.empty())
+        HIP_TRY(hipMemcpyAsync(c->d_live, c->live.data(), sizeof(int) * c->live.size(), hipMemcpyHostToDevice, c->stream));
+    for (int i = 0; i < n; ++i) {
+        if (!c->reps[i].live) continue;
+        HIP_TRY(hipMemcpyAsync(c->d_desc + i, &c->reps[i].d, sizeof(RepDesc), hipMemcpyHostToDevice, c->stream));
+    }
+    HIP_TRY(hipStreamSynchronize(c->stream));
+    c->n_main = (long)M.size();
+    c->n_seam = (long)S.size();
+    c->dirty = false;
+    c->graph_valid = false;
+    return ISLF_OK;
+}
+
+// init spins + initial observables of slot i (synchronises)
+static islf_status init_replica(islf_ctx *c, int i, int mode, const int8_t *host_staged)
+{
+    Replica &R = c->reps[i];
+    HIP_TRY(hipMemcpyAsync(c->d_desc + i, &R.d, sizeof(RepDesc), hipMemcpyHostToDevice, c->stream));
+    HIP_TRY(launch_zero((unsigned long long *)R.d.acc, 2 * kAccSlots * 4, c->stream));
+    HIP_TRY(launch_init(c->fmt, c->d_desc, i, mode, host_staged, c->stream));
+    const size_t N = (size_t)R.desc.Lx * R.desc.Ly * R.desc.Lz;
+    int8_t *tmp = (int8_t *)dev_alloc(c, N);
+    if (!tmp) return fail(ISLF_ENOMEM, "cannot allocate %zu bytes of staging", N);
+    hipError_t e = launch_export(c->d_desc, i, tmp, c->stream);
+    if (e == hipSuccess) e = launch_recompute(c->d_desc, i, tmp, c->d_scratch, c->stream);
+    if (e == hipSuccess) e = launch_set_state(c->d_state, i, c->d_scratch, 0u, c->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+    dev_free(c, tmp);
+    if (e != hipSuccess) return fail(ISLF_EDEVICE, "replica init failed: %s", hipGetErrorString(e));
+    R.t_host = 0;
+    return ISLF_OK;
+}
+
+static islf_status add_replica(islf_ctx *c, const islf_replica_desc *desc, int *slot_out)
+{
+    islf_status st = validate(desc);
+    if (st != ISLF_OK) return st;
+    int slot = -1;
+    for (int i = 0; i < (int)c->reps.size(); ++i)
+        if (!c->reps[i].live) {
+            slot = i;
+            break;
+        }
+    if (slot < 0) {
+        slot = (int)c->reps.size();
+        c->reps.emplace_back();
+    }
+    st = ensure_slots(c, (int)c->reps.size());
+    if (st != ISLF_OK) return st;
+    Replica &R = c->reps[slot];
+    R.desc = *desc;
+    const size_t bytes = replica_bytes(desc, c->fmt, c->cap);
+    if (R.mem && R.mem_bytes < bytes) {
+        dev_free(c, R.mem);
+        R.mem = nullptr;
+    }
+    if (!R.mem) {
+        R.mem = dev_alloc(c, bytes);
+        if (!R.mem) return fail(ISLF_ENOMEM, "cannot allocate %zu device bytes for a replica", bytes);
+        R.mem_bytes = bytes;
+    }
+    R.tile = default_tile(desc, c->fmt);
+    fill_desc(R, c->fmt, c->cap);
+    build_work(R, slot, c->fmt);
+    const int mode = desc->init == ISLF_INIT_HOST ? ISLF_INIT_UP : desc->init;
+    st = init_replica(c, slot, mode, nullptr);
+    if (st != ISLF_OK) return st;
+    R.live = true;
+    c->dirty = true;
+    *slot_out = slot;
+    return ISLF_OK;
+}
+
+static void destroy_ctx(islf_ctx *c)
+{
+    if (!c) return;
+    if (c->stream || true) (void)hipStreamSynchronize(c->stream);
+    if (c->graph_exec) (void)hipGraphExecDestroy(c->graph_exec);
+    if (c->graph) (void)hipGraphDestroy(c->graph);
+    for (auto &R : c->reps) dev_free(c, R.mem);
+    dev_free(c, c->d_desc);
+    dev_free(c, c->d_state);
+    dev_free(c, c->d_sync);
+    dev_free(c, c->d_scratch);
+    dev_free(c, c->d_live);
+    dev_free(c, c->d_main);
+    dev_free(c, c->d_seam);
+    delete c;
+}
+
+// ---------------------------------------------------------------------------
+// public API
+// ---------------------------------------------------------------------------
+extern "C" islf_status islf_create_with_allocator(const islf_replica_desc *reps, int32_t n_reps,
+                                                  int32_t spin_format, uint32_t obs_capacity,
+                                                  void *hip_stream, islf_alloc_fn alloc,
+                                                  islf_free_fn free_fn, void *user, islf_ctx **out)
+{
+    if (!out) return fail(ISLF_EINVAL, "NULL output pointer");
+    *out = nullptr;
+    if (!reps || n_reps < 1) return fail(ISLF_EINVAL, "need at least one replica");
+    if (spin_format != ISLF_SPIN_INT8 && spin_format != ISLF_SPIN_BITPACK)
+        return fail(ISLF_EINVAL, "invalid spin format %d", spin_format);
+    if (obs_capacity < 1) return fail(ISLF_EINVAL, "obs_capacity must be >= 1");
+    if ((alloc == nullptr) != (free_fn == nullptr)) return fail(ISLF_EINVAL, "give both alloc and free or neither");
+    for (int i = 0; i < n_reps; ++i) {
+        islf_status st = validate(&reps[i]);
+        if (st != ISLF_OK) return st;
+    }
+    islf_ctx *c = new islf_ctx();
+    c->fmt = spin_format;
+    c->cap = obs_capacity;
+    c->stream = (hipStream_t)hip_stream;
+    c->alloc = alloc;
+    c->free_fn = free_fn;
+    c->user = user;
+    int dev = 0;
+    hipDeviceProp_t prop;
+    if (hipGetDevice(&dev) != hipSuccess || hipGetDeviceProperties(&prop, dev) != hipSuccess) {
+        delete c;
+        return fail(ISLF_EDEVICE, "no HIP device");
+    }
+    c->num_cu = prop.multiProcessorCount;
+    c->max_grid = c->num_cu * 8;
+    int per_cu = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, persistent_kernel(spin_format), kBlock, 0) != hipSuccess ||
+        per_cu < 1)
+        per_cu = 1;
+    c->persistent_grid = c->num_cu * std::min(per_cu, 8);
+    c->d_sync = (GridSync *)dev_alloc(c, sizeof(GridSync));
+    c->d_scratch = (unsigned long long *)dev_alloc(c, 64 * sizeof(unsigned long long));
+    if (!c->d_sync || !c->d_scratch) {
+        destroy_ctx(c);
+        return fail(ISLF_ENOMEM, "cannot allocate context buffers");
+    }
+    if (launch_zero((unsigned long long *)c->d_sync, sizeof(GridSync) / 8, c->stream) != hipSuccess) {
+        destroy_ctx(c);
+        return fail(ISLF_EDEVICE, "cannot clear sync words");
+    }
+    for (int i = 0; i < n_reps; ++i) {
+        int slot;
+        islf_status st = add_replica(c, &reps[i], &slot);
+        if (st != ISLF_OK) {
+            std::string keep = g_err;
+            destroy_ctx(c);
+            g_err = keep;
+            return st;
+        }
+    }
+    islf_status st = sync_tables(c);
+    if (st != ISLF_OK) {
+        std::string keep = g_err;
+        destroy_ctx(c);
+        g_err = keep;
+        return st;
+    }
+    *out = c;
+    return ISLF_OK;
+}
+
+extern "C" islf_status islf_create(const islf_replica_desc *reps, int32_t n_reps, int32_t spin_format,
+                                   uint32_t obs_capacity, void *hip_stream, islf_ctx **out)
+{
+    return islf_create_with_allocator(reps, n_reps, spin_format, obs_capacity, hip_stream, nullptr, nullptr,
+                                      nullptr, out);
+}
+
+extern "C" islf_status islf_destroy(islf_ctx *ctx)
+{
+    if (!ctx) return fail(ISLF_EINVAL, "NULL context");
+    destroy_ctx(ctx);
+    return ISLF_OK;
+}
+
+extern "C" islf_status islf_num_replicas(const islf_ctx *ctx, int32_t *n)
+{
+    if (!ctx || !n) return fail(ISLF_EINVAL, "NULL argument");
+    *n = (int32_t)ctx->reps.size();
+    return ISLF_OK;
+}
+
+static islf_status check_rep(const islf_ctx *ctx, int32_t rep)
+{
+    if (!ctx) return fail(ISLF_EINVAL, "NULL context");
+    if (rep < 0 || rep >= (int32_t)ctx->reps.size() || !ctx->reps[rep].live)
+        return fail(ISLF_ERANGE, "replica %d is not live", rep);
+    return ISLF_OK;
+}
+
+extern "C" islf_status islf_get_desc(const islf_ctx *ctx, int32_t rep, islf_replica_desc *out)
+{
+    islf_status st = check_rep(ctx, rep);
+    if (st != ISLF_OK) return st;
+    if (!out) return fail(ISLF_EINVAL, "NULL output");
+    *out = ctx->reps[rep].desc;
+    return ISLF_OK;
+}
+
+extern "C" islf_status islf_set_spins(islf_ctx *ctx, int32_t rep, const int8_t *host, size_t n)
+{
+    islf_status st = check_rep(ctx, rep);
+    if (st != ISLF_OK) return st;
+    Replica &R = ctx->reps[rep];
+    const size_t N = (size_t)R.desc.Lx * R.desc.Ly * R.desc.Lz;
+    if (!host || n != N) return fail(ISLF_EINVAL, "expected %zu spins, got %zu", N, n);
+    if (R.t_host != 0) return fail(ISLF_ESTATE, "set_spins is only valid before the first sweep");
+    for (size_t i = 0; i < n; ++i)
+        if (host[i] != 1 && host[i] != -1) return fail(ISLF_EINVAL, "spin %zu is %d, not +-1", i, (int)host[i]);
+    int8_t *staged = (int8_t *)dev_alloc(ctx, N);
+    if (!staged) return fail(ISLF_ENOMEM, "cannot allocate staging");
+    hipError_t e = hipMemcpyAsync(staged, host, N, hipMemcpyHostToDevice, ctx->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(ctx->stream);
+    if (e != hipSuccess) {
+        dev_free(ctx, staged);
+        return fail(ISLF_EDEVICE, "copy of host spins failed: %s", hipGetErrorString(e));
+    }
+    st = init_replica(ctx, rep, 3, staged);
+    dev_free(ctx, staged);
+    return st;
+}
+
+extern "C" islf_status islf_get_spins(islf_ctx *ctx, int32_t rep, int8_t *host, size_t n)
+{
+    islf_status st = check_rep(ctx, rep);
+    if (st != ISLF_OK) return st;
+    Replica &R = ctx->reps[rep];
+    const size_t N = (size_t)R.desc.Lx * R.desc.Ly * R.desc.Lz;
+    if (!host || n != N) return fail(ISLF_EINVAL, "expected %zu spins, got %zu", N, n);
+    int8_t *tmp = (int8_t *)dev_alloc(ctx, N);
+    if (!tmp) return fail(ISLF_ENOMEM, "cannot allocate staging");
+    hipError_t e = launch_export(ctx->d_desc, rep, tmp, ctx->stream);
+    if (e == hipSuccess) e = hipMemcpyAsync(host, tmp, N, hipMemcpyDeviceToHost, ctx->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(ctx->stream);
+    dev_free(ctx, tmp);
+    if (e != hipSuccess) return fail(ISLF_EDEVICE, "get_spins failed: %s", hipGetErrorString(e));
+    return ISLF_OK;
+}
+
+extern "C" islf_status islf_set_exec(islf_ctx *ctx, int32_t mode)
+{
+    if (!ctx) return fail(ISLF_EINVAL, "NULL context");
+    if (mode < ISLF_EXEC_PLAIN || mode > ISLF_EXEC_PERSISTENT) return fail(ISLF_EINVAL, "invalid exec mode %d", mode);
+    ctx->exec = mode;
+    return ISLF_OK;
+}
+
+// Enqueues n sweeps in the context's execution form (no checks, no sync).
+static islf_status enqueue_sweeps(islf_ctx *c, uint32_t n)
+{
+    const int nl = (int)c->live.size();
+    if (nl == 0 || n == 0) return ISLF_OK;
+    if (c->exec == ISLF_EXEC_PERSISTENT) {
+        hipError_t e = launch_persistent(c->fmt, c->d_desc, c->d_state, c->d_main, c->n_main, c->d_seam, c->n_seam,
+                                         c->d_live, nl, n, c->d_sync, c->persistent_grid, c->stream);
+        if (e != hipSuccess) return fail(ISLF_EDEVICE, "persistent launch failed: %s", hipGetErrorString(e));
+        return ISLF_OK;
+    }
+    for (uint32_t s = 0; s < n; ++s) {
+        for (int p = 0; p < 4; ++p) {
+            const bool seam = p >= 2;
+            if (c->exec == ISLF_EXEC_BATCHED) {
+                HIP_TRY(launch_phase(c->fmt, c->d_desc, c->d_state, seam ? c->d_seam : c->d_main,
+                                     seam ? c->n_seam : c->n_main, p, c->max_grid, c->stream));
+            } else {
+                for (int r : c->live) {
+                    const Entry *w = seam ? c->d_seam + c->seam_off[r] : c->d_main + c->main_off[r];
+                    const long len = seam ? c->seam_len[r] : c->main_len[r];
+                    HIP_TRY(launch_phase(c->fmt, c->d_desc, c->d_state, w, len, p, c->max_grid, c->stream));
+                }
+            }
+        }
+        HIP_TRY(launch_end_sweep(c->d_desc, c->d_state, c->d_live, nl, c->stream));
+    }
+    return ISLF_OK;
+}
+
+static islf_status check_sweep_range(islf_ctx *c, uint64_t n)
+{
+    for (int r : c->live)
+        if (c->reps[r].t_host + n > 0xFFFFFFFFull)
+            return fail(ISLF_ERANGE, "replica %d would pass 2^32-1 sweeps", r);
+    return ISLF_OK;
+}
+
+extern "C" islf_status islf_sweep(islf_ctx *ctx, uint32_t n_sweeps)
+{
+    if (!ctx) return fail(ISLF_EINVAL, "NULL context");
+    islf_status st = sync_tables(ctx);
+    if (st != ISLF_OK) return st;
+    st = check_sweep_range(ctx, n_sweeps);
+    if (st != ISLF_OK) return st;
+    st = enqueue_sweeps(ctx, n_sweeps);
+    if (st != ISLF_OK) return st;
+    for (int r : ctx->live) ctx->reps[r].t_host += n_sweeps;
+    return ISLF_OK;
+}
+
+static islf_status check_device_error(islf_ctx *c)
+{
+    GridSync h;
+    HIP_TRY(hipMemcpyAsync(&h, c->d_sync, sizeof(unsigned int) * 4, hipMemcpyDeviceToHost, c->stream));
+    HIP_TRY(hipStreamSynchronize(c->stream));
+    if (h.error) return fail(ISLF_EDEVICE, "a persistent-kernel barrier timed out");
+    return ISLF_OK;
+}
+
+extern "C" islf_status islf_sweep_count(islf_ctx *ctx, int32_t rep, uint64_t *t)
+{
+    islf_status st = check_rep(ctx, rep);
+    if (st != ISLF_OK) return st;
+    if (!t) return fail(ISLF_EINVAL, "NULL output");
+    RepState s;
+    HIP_TRY(hipMemcpyAsync(&s, ctx->d_state + rep, sizeof s, hipMemcpyDeviceToHost, ctx->stream));
+    HIP_TRY(hipStreamSynchronize(ctx->stream));
+    st = check_device_error(ctx);
+    if (st != ISLF_OK) return st;
+    if (s.t != (uint32_t)ctx->reps[rep].t_host)
+        return fail(ISLF_EDEVICE, "device sweep counter %u != issued %llu", s.t,
+                    (unsigned long long)ctx->reps[rep].t_host);
+    *t = s.t;
+    return ISLF_OK;
+}
+
+static islf_status check_records(islf_ctx *c, int rep, uint64_t first, uint32_t count)
+{
+    const uint64_t t = c->reps[rep].t_host;
+    if (count == 0) return fail(ISLF_EINVAL, "count must be >= 1");
+    if (first + count > t) return fail(ISLF_ERANGE, "records up to sweep %llu requested, %llu run",
+                                       (unsigned long long)(first + count), (unsigned long long)t);
+    if (t > c->cap && first < t - c->cap)
+        return fail(ISLF_ERANGE, "record %llu has left the ring (capacity %u)", (unsigned long long)first, c->cap);
+    return ISLF_OK;
+}
+
+extern "C" islf_status islf_measure(islf_ctx *ctx, int32_t rep, uint64_t first, uint32_t count, islf_obs *out)
+{
+    islf_status st = check_rep(ctx, rep);
+    if (st != ISLF_OK) return st;
+    if (!out) return fail(ISLF_EINVAL, "NULL output");
+    st = check_records(ctx, rep, first, count);
+    if (st != ISLF_OK) return st;
+    const Replica &R = ctx->reps[rep];
+    uint32_t done = 0;
+    while (done < count) {
+        const uint32_t slot = (uint32_t)((first + done) % ctx->cap);
+        const uint32_t n = std::min<uint32_t>(count - done, ctx->cap - slot);
+        HIP_TRY(hipMemcpyAsync(out + done, R.d.rec + slot, n * sizeof(islf_obs), hipMemcpyDeviceToHost, ctx->stream));
+        done += n;
+    }
+    HIP_TRY(hipStreamSynchronize(ctx->stream));
+    return check_device_error(ctx);
+}
+
+extern "C" islf_status islf_recompute(islf_ctx *ctx, int32_t rep, islf_obs *out)
+{
+    islf_status st = check_rep(ctx, rep);
+    if (st != ISLF_OK) return st;
+    if (!out) return fail(ISLF_EINVAL, "NULL output");
+    const Replica &R = ctx->reps[rep];
+    const size_t N = (size_t)R.desc.Lx * R.desc.Ly * R.desc.Lz;
+    int8_t *tmp = (int8_t *)dev_alloc(ctx, N);
+    if (!tmp) return fail(ISLF_ENOMEM, "cannot allocate staging");
+    unsigned long long h[4];
+    hipError_t e = launch_export(ctx->d_desc, rep, tmp, ctx->stream);
+    if (e == hipSuccess) e = launch_recompute(ctx->d_desc, rep, tmp, ctx->d_scratch, ctx->stream);
+    if (e == hipSuccess) e = hipMemcpyAsync(h, ctx->d_scratch, sizeof h, hipMemcpyDeviceToHost, ctx->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(ctx->stream);
+    dev_free(ctx, tmp);
+    if (e != hipSuccess) return fail(ISLF_EDEVICE, "recompute failed: %s", hipGetErrorString(e));
+    out->B = (int64_t)h[0];
+    out->M = (int64_t)h[1];
+    out->M1 = (int64_t)h[2];
+    out->Mn = (int64_t)h[3];
+    return ISLF_OK;
+}
+
+extern "C" islf_status islf_energy(islf_ctx *ctx, int32_t rep, uint64_t first, uint32_t count, double *out)
+{
+    islf_status st = check_rep(ctx, rep);
+    if (st != ISLF_OK) return st;
+    if (!out) return fail(ISLF_EINVAL, "NULL output");
+    st = check_records(ctx, rep, first, count);
+    if (st != ISLF_OK) return st;
+    const Replica &R = ctx->reps[rep];
+    double *tmp = (double *)dev_alloc(ctx, sizeof(double) * count);
+    if (!tmp) return fail(ISLF_ENOMEM, "cannot allocate staging");
+    hipError_t e = launch_energy(R.d.rec, ctx->cap, first, count, R.desc.J, R.desc.H, R.desc.h1, R.desc.hn, tmp,
+                                 ctx->stream);
+    if (e == hipSuccess) e = hipMemcpyAsync(out, tmp, sizeof(double) * count, hipMemcpyDeviceToHost, ctx->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(ctx->stream);
+    dev_free(ctx, tmp);
+    if (e != hipSuccess) return fail(ISLF_EDEVICE, "energy failed: %s", hipGetErrorString(e));
+    return ISLF_OK;
+}
+
+extern "C" islf_status islf_means(islf_ctx *ctx, uint64_t first, uint32_t count, double *out)
+{
+    if (!ctx || !out) return fail(ISLF_EINVAL, "NULL argument");
+    islf_status st = sync_tables(ctx);
+    if (st != ISLF_OK) return st;
+    const int n = (int)ctx->reps.size();
+    for (int r = 0; r < n; ++r) {
+        if (!ctx->reps[r].live) continue;
+        st = check_records(ctx, r, first, count);
+        if (st != ISLF_OK) return st;
+    }
+    // live replicas only; dead slots report NaN
+    const int nl = (int)ctx->live.size();
+    std::vector<double> tmp_h(5 * (size_t)std::max(nl, 1));
+    double *tmp = (double *)dev_alloc(ctx, sizeof(double) * 5 * std::max(nl, 1));
+    if (!tmp) return fail(ISLF_ENOMEM, "cannot allocate staging");
+    hipError_t e = hipSuccess;
+    if (nl > 0) e = launch_means(ctx->d_desc, ctx->d_live, nl, first, count, tmp, ctx->stream);
+    if (e == hipSuccess && nl > 0)
+        e = hipMemcpyAsync(tmp_h.data(), tmp, sizeof(double) * 5 * nl, hipMemcpyDeviceToHost, ctx->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(ctx->stream);
+    dev_free(ctx, tmp);
+    if (e != hipSuccess) return fail(ISLF_EDEVICE, "means failed: %s", hipGetErrorString(e));
+    for (int r = 0; r < n; ++r)
+        for (int k = 0; k < 5; ++k) out[5 * r + k] = NAN;
+    for (int i = 0; i < nl; ++i)
+        for (int k = 0; k < 5; ++k) out[5 * ctx->live[i] + k] = tmp_h[5 * i + k];
+    return ISLF_OK;
+}
+
+extern "C" islf_status islf_integrate(const double *h, const double *m1, const double *mn, int32_t n, double c1,
+                                      double cn, double norm, double *out, void *hip_stream)
+{
+    if (!h || !m1 || !mn || !out) return fail(ISLF_EINVAL, "NULL argument");
+    if (n < 1) return fail(ISLF_EINVAL, "need n >= 1 points");
+    HIP_TRY(launch_integrate(h, m1, mn, n, c1, cn, norm, out, (hipStream_t)hip_stream));
+    return ISLF_OK;
+}
+
+extern "C" islf_status islf_footprint_bytes(const islf_replica_desc *desc, int32_t spin_format,
+                                            uint32_t obs_capacity, uint64_t *bytes)
+{
+    if (!bytes) return fail(ISLF_EINVAL, "NULL output");
+    islf_status st = validate(desc);
+    if (st != ISLF_OK) return st;
+    if (spin_format != ISLF_SPIN_INT8 && spin_format != ISLF_SPIN_BITPACK)
+        return fail(ISLF_EINVAL, "invalid spin format %d", spin_format);
+    Replica R;
+    R.desc = *desc;
+    R.tile = default_tile(desc, spin_format);
+    build_work(R, 0, spin_format);
+    *bytes = replica_bytes(desc, spin_format, obs_capacity) + sizeof(Entry) * (R.main.size() + R.seam.size()) +
+             sizeof(RepDesc) + sizeof(RepState);
+    return ISLF_OK;
+}
+
+extern "C" islf_status islf_batch_add(islf_ctx *ctx, const islf_replica_desc *desc, int32_t *slot)
+{
+    if (!ctx || !slot) return fail(ISLF_EINVAL, "NULL argument");
+    int s = -1;
+    islf_status st = add_replica(ctx, desc, &s);
+    if (st != ISLF_OK) return st;
+    *slot = s;
+    return sync_tables(ctx);
+}
+
+extern "C" islf_status islf_batch_retire(islf_ctx *ctx, int32_t slot)
+{
+    islf_status st = check_rep(ctx, slot);
+    if (st != ISLF_OK) return st;
+    HIP_TRY(hipStreamSynchronize(ctx->stream));
+    Replica &R = ctx->reps[slot];
+    R.live = false;
+    R.t_host = 0;
+    ctx->dirty = true;
+    // the slot's memory is kept for reuse by the next admission
+    return sync_tables(ctx);
+}
+
+extern "C" islf_status islf_graph_capture(islf_ctx *ctx, uint32_t k_sweeps)
+{
+    if (!ctx) return fail(ISLF_EINVAL, "NULL context");
+    if (k_sweeps < 1) return fail(ISLF_EINVAL, "k_sweeps must be >= 1");
+    if (!ctx->stream) return fail(ISLF_ESTATE, "graph capture needs a non-default stream");
+    islf_status st = sync_tables(ctx);
+    if (st != ISLF_OK) return st;
+    if (ctx->graph_exec) {
+        (void)hipGraphExecDestroy(ctx->graph_exec);
+        ctx->graph_exec = nullptr;
+    }
+    if (ctx->graph) {
+        (void)hipGraphDestroy(ctx->graph);
+        ctx->graph = nullptr;
+    }
+    ctx->graph_valid = false;
+    HIP_TRY(hipStreamBeginCapture(ctx->stream, hipStreamCaptureModeThreadLocal));
+    st = enqueue_sweeps(ctx, k_sweeps);
+    hipGraph_t g = nullptr;
+    hipError_t e = hipStreamEndCapture(ctx->stream, &g);
+    if (st != ISLF_OK) {
+        if (g) (void)hipGraphDestroy(g);
+        return st;
+    }
+    if (e != hipSuccess) return fail(ISLF_EDEVICE, "graph capture failed: %s", hipGetErrorString(e));
+    ctx->graph = g;
+    HIP_TRY(hipGraphInstantiate(&ctx->graph_exec, g, nullptr, nullptr, 0));
+    ctx->graph_sweeps = k_sweeps;
+    ctx->graph_valid = true;
+    return ISLF_OK;
+}
+
+extern "C" islf_status islf_run_graph(islf_ctx *ctx, uint32_t n_replays)
+{
+    if (!ctx) return fail(ISLF_EINVAL, "NULL context");
+    if (!ctx->graph_valid || ctx->dirty) return fail(ISLF_ESTATE, "no valid captured graph");
+    islf_status st = check_sweep_range(ctx, (uint64_t)ctx->graph_sweeps * n_replays);
+    if (st != ISLF_OK) return st;
+    for (uint32_t i = 0; i < n_replays; ++i) HIP_TRY(hipGraphLaunch(ctx->graph_exec, ctx->stream));
+    for (int r : ctx->live) ctx->reps[r].t_host += (uint64_t)ctx->graph_sweeps * n_replays;
+    return ISLF_OK;
+}
+
+extern "C" islf_status islf_num_tiles(int32_t spin_format, int32_t *n)
+{
+    if (!n) return fail(ISLF_EINVAL, "NULL output");
+    if (spin_format != ISLF_SPIN_INT8 && spin_format != ISLF_SPIN_BITPACK)
+        return fail(ISLF_EINVAL, "invalid spin format %d", spin_format);
+    *n = num_tiles_of(spin_format);
+    return ISLF_OK;
+}
+
+extern "C" islf_status islf_get_tile(const islf_ctx *ctx, int32_t rep, int32_t *tile)
+{
+    islf_status st = check_rep(ctx, rep);
+    if (st != ISLF_OK) return st;
+    if (!tile) return fail(ISLF_EINVAL, "NULL output");
+    *tile = ctx->reps[rep].tile;
+    return ISLF_OK;
+}
+
+extern "C" islf_status islf_set_tile(islf_ctx *ctx, int32_t rep, int32_t tile)
+{
+    islf_status st = check_rep(ctx, rep);
+    if (st != ISLF_OK) return st;
+    if (tile < 0 || tile >= num_tiles_of(ctx->fmt)) return fail(ISLF_EINVAL, "tile %d out of range", tile);
+    Replica &R = ctx->reps[rep];
+    R.tile = tile;
+    build_work(R, rep, ctx->fmt);
+    ctx->dirty = true;
+    return ISLF_OK;
+}
+
+extern "C" islf_status islf_autotune(islf_ctx *ctx, uint32_t sweeps)
+{
+    (void)ctx;
+    (void)sweeps;
+    return fail(ISLF_ESTATE, "autotune not available yet");
+}

@@ -1,0 +1,69 @@
+// Internal data structures shared by the host side and the gfx950 kernels of
+// libislf.  Not part of the public ABI.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "../../include/islf.h"
+
+namespace islf {
+
+constexpr int kBlock = 256;          // threads per workgroup of the update kernels
+constexpr int kAccSlots = 64;        // spread of the per-sweep partial-sum atomics
+constexpr int kClasses = 4;          // bulk, x = 0, x = Lx-1, one-layer film
+constexpr int kThrPerClass = 16;     // index u*8 + cnt, cnt in 0..6
+constexpr int kThrEntries = kClasses * kThrPerClass;
+constexpr int kPadEntry = kThrEntries - 1;   // class 3, u = 1, cnt = 7: never a real site
+constexpr int kMaxMarch = 256;       // x planes one thread may march through per entry
+
+// One tile of work for one replica: a box of rows/columns starting at
+// (x0, y0, j0) whose extent is the replica's tile shape.  j counts 8-byte
+// chunks (int8 format) or 32-bit words of one sublattice row (bit-packed).
+struct Entry {
+    int32_t rep, x0, y0, j0;
+};
+
+// Read-only description of a replica as the kernels see it.
+struct RepDesc {
+    uint8_t *spins;        // int8 format: byte 1 = up, 0 = down; rows of Lzp bytes
+                           // bit-packed: rows of 2*Wq uint32 words (even z, odd z)
+    islf_obs *rec;         // ring of cap per-sweep records
+    long long *acc;        // 2 x kAccSlots x 4 partial sums (double-buffered by t & 1)
+    uint64_t thr[kThrEntries];  // acceptance thresholds, index class*16 + u*8 + cnt
+    uint32_t thr_m1[kThrEntries];  // thr - 1 (accept iff u <= thr_m1) where thr >= 1
+    int32_t dpack[kThrEntries];    // change of (B, M) on a flip: dB + 65536 * dM
+    uint64_t never_mask;           // bit i set when thr[i] == 0 (no draw can accept)
+    int32_t Lx, Ly, Lz;
+    int32_t C;             // chunks of 8 sites per row, ceil(Lz/8)
+    int32_t Lzp;           // int8 row stride in bytes, 8*C
+    int32_t Wq;            // bit-packed words per sublattice row, ceil(Lz/64)
+    int32_t seam_reflect;  // 1: the y seam maps x -> Lx-1-x
+    int32_t seam_invert;   // 1: the y seam carries eps = -1
+    uint32_t key0, key1, replica, cap;
+    int32_t tile_lj, tile_ly;      // bit-packed main phases: log2 tile extent along j and y
+    int32_t tile_lj_seam;          // seam phases: log2 tile extent along j
+    int32_t fmt;                   // islf_spin_format
+    int32_t i8_tj, i8_ty, i8_mx;   // int8 main phases: chunks x rows per workgroup, x planes marched
+    int32_t pad_[1];
+    double J, H, h1, hn;           // for energies (Eq. 1)
+};
+
+// Mutable per-replica state (device memory).
+struct RepState {
+    long long cur[4];      // observables after the last completed sweep
+    uint32_t t;            // completed sweeps
+    uint32_t live;
+    uint32_t pad_[2];
+};
+
+// Persistent-kernel synchronisation words (device memory, zero-initialised).
+// The arrival counter only ever changes through read-modify-write atomics
+// (it is re-zeroed by a fill kernel before each persistent launch).
+struct GridSync {
+    unsigned long long count;
+    unsigned int error;
+    unsigned int pad_[61];
+};
+
+}  // namespace islf

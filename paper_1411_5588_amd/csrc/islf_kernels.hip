@@ -1,0 +1,996 @@
+// gfx950 kernels of libislf: checkerboard Metropolis sweeps of the thin-film
+// Ising model (arXiv:1411.5588, Sec. II.A Eq. 1 with the y boundaries of
+// Eq. 11; Appendix: checkerboard update), fused observable reductions, random
+// initial states, full-recompute observables, record bookkeeping, means and
+// the field thermodynamic integration (Eq. 9 / Eq. 22).
+//
+// The path is integer stencil work plus Philox4x32-10: no matrix cores.  Two
+// spin formats:
+//  * int8: one byte per site, 1 = up, 0 = down, rows of Lzp = 8*ceil(Lz/8)
+//    bytes, z fastest, row index x*Ly + y.  A thread owns one 8-byte chunk of
+//    a row: the 4 sites of the current phase in it share one Philox call, and
+//    the neighbour counts of all 8 bytes are formed with plain 64-bit adds
+//    (each byte holds 0/1, sums stay below 8, so no carry crosses a byte).
+//  * bit-packed: one bit per site, each row split into its even-z and odd-z
+//    sublattices of Lz/2 bits.  A thread owns one 32-bit word of one
+//    sublattice row (32 sites of the same phase, 8 Philox calls); neighbour
+//    counts are bit-sliced with full adders.
+// Both formats draw the same Philox word for the same site, so they give the
+// same Markov chain.
+#include "islf_internal.h"
+
+#pragma clang fp contract(off)
+
+namespace islf {
+
+__device__ __forceinline__ uint32_t xor3(uint32_t a, uint32_t b, uint32_t c)
+{
+    return a ^ b ^ c;
+}
+
+// ---------------------------------------------------------------------------
+// Philox4x32-10 (Salmon et al., SC'11): ten rounds of two 32x32->64 multiplies
+// whose halves are xored into the other counter words with the round key; the
+// key advances by the Weyl constants after each round.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ void philox10(uint32_t c0, uint32_t c1, uint32_t c2, uint32_t c3,
+                                         uint32_t k0, uint32_t k1, uint32_t out[4])
+{
+#pragma unroll
+    for (int r = 0; r < 10; ++r) {
+        const uint64_t pa = (uint64_t)0xD2511F53u * c0;
+        const uint64_t pb = (uint64_t)0xCD9E8D57u * c2;
+        const uint32_t n0 = xor3((uint32_t)(pb >> 32), c1, k0);
+        const uint32_t n2 = xor3((uint32_t)(pa >> 32), c3, k1);
+        c1 = (uint32_t)pb;
+        c3 = (uint32_t)pa;
+        c0 = n0;
+        c2 = n2;
+        k0 += 0x9E3779B9u;
+        k1 += 0xBB67AE85u;
+    }
+    out[0] = c0; out[1] = c1; out[2] = c2; out[3] = c3;
+}
+
+constexpr uint64_t kOnes8 = 0x0101010101010101ull;
+
+__device__ __forceinline__ uint32_t bytesum64(uint64_t v)
+{
+    return __builtin_amdgcn_sad_u8((uint32_t)v, 0u, __builtin_amdgcn_sad_u8((uint32_t)(v >> 32), 0u, 0u));
+}
+
+struct Acc {
+    int dB, dM, dM1, dMn;
+};
+
+// Wave64 + workgroup reduction of the four partial sums, then one atomic add
+// per quantity into the replica's spread accumulator of the current sweep.
+__device__ void flush_acc(Acc &a, long long *acc_base, uint32_t t, int slot)
+{
+    __shared__ int red[4][kBlock / 64];
+    int v[4] = {a.dB, a.dM, a.dM1, a.dMn};
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+#pragma unroll
+        for (int off = 32; off > 0; off >>= 1) v[k] += __shfl_xor(v[k], off, 64);
+    }
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    if (lane == 0) {
+#pragma unroll
+        for (int k = 0; k < 4; ++k) red[k][wave] = v[k];
+    }
+    __syncthreads();
+    if (threadIdx.x < 4) {
+        int s = 0;
+#pragma unroll
+        for (int w = 0; w < kBlock / 64; ++w) s += red[threadIdx.x][w];
+        if (s != 0) {
+            long long *dst = acc_base + ((size_t)(t & 1) * kAccSlots + slot) * 4 + threadIdx.x;
+            atomicAdd((unsigned long long *)dst, (unsigned long long)(long long)s);
+        }
+    }
+    __syncthreads();
+    a.dB = a.dM = a.dM1 = a.dMn = 0;
+}
+
+// Per-replica lookup tables staged in LDS: 64-bit thresholds (used by the
+// seam and bit-packed paths and by replicas with never-accepted moves),
+// thr - 1 as 32 bits and the packed (dB, dM) change of a flip.
+struct TD {
+    uint32_t thr_m1;
+    int32_t dpack;
+};
+struct Tables {
+    uint64_t thr[kThrEntries];
+    TD td[kThrEntries];
+};
+
+__device__ __forceinline__ void load_tables(const RepDesc &d, Tables *t)
+{
+    for (int k = threadIdx.x; k < kThrEntries; k += blockDim.x) {
+        t->thr[k] = d.thr[k];
+        t->td[k].thr_m1 = d.thr_m1[k];
+        t->td[k].dpack = d.dpack[k];
+    }
+}
+
+// Per-replica parameters as the update loop uses them: loaded once per
+// replica change from the descriptor table, uniform across the workgroup (the
+// compiler keeps them in scalar registers).
+struct RepView {
+    uint8_t *spins;
+    long long *acc;
+    int Lx, Ly, Lz, C, Wq;
+    uint32_t Lzp;           // int8 row stride in bytes
+    int seam_reflect, seam_invert;
+    uint32_t key0, key1, replica, t;
+    int lj, ly;
+    int tj, ty, mx;          // int8 marching tile
+    bool never;              // some move can never be accepted (thr == 0)
+};
+
+__device__ __forceinline__ RepView load_view(const RepDesc *__restrict__ descs, const RepState *__restrict__ st,
+                                             int rep, bool seam, uint32_t t_offset)
+{
+    const RepDesc &d = descs[rep];
+    RepView v;
+    v.spins = d.spins;
+    v.acc = d.acc;
+    v.Lx = d.Lx; v.Ly = d.Ly; v.Lz = d.Lz; v.C = d.C; v.Wq = d.Wq;
+    v.Lzp = (uint32_t)d.Lzp;
+    v.seam_reflect = d.seam_reflect;
+    v.seam_invert = d.seam_invert;
+    v.key0 = d.key0; v.key1 = d.key1; v.replica = d.replica;
+    v.t = st[rep].t + t_offset;
+    v.lj = seam ? d.tile_lj_seam : d.tile_lj;
+    v.ly = seam ? 0 : d.tile_ly;
+    v.tj = d.i8_tj;
+    v.ty = d.i8_ty;
+    v.mx = d.i8_mx;
+    v.never = d.never_mask != 0;
+    return v;
+}
+
+// ---------------------------------------------------------------------------
+// int8 format: update the current-phase sites of one 8-byte chunk.
+// Byte offsets are 32-bit (a replica's spin array is below 4 GiB).
+// ---------------------------------------------------------------------------
+// Loads through the global address space (the spin arrays always live in
+// device memory), addressed as a uniform base plus a 32-bit offset.
+typedef __attribute__((address_space(1))) const uint8_t gcu8;
+typedef __attribute__((address_space(1))) const uint32_t gcu32;
+typedef __attribute__((address_space(1))) const uint64_t gcu64;
+typedef __attribute__((address_space(1))) uint64_t gu64;
+typedef __attribute__((address_space(1))) uint32_t gu32;
+
+__device__ __forceinline__ uint64_t ld64(const uint8_t *base, uint32_t off)
+{
+    return *(gcu64 *)((gcu8 *)base + off);
+}
+__device__ __forceinline__ uint64_t ld8(const uint8_t *base, uint32_t off)
+{
+    return *((gcu8 *)base + off);
+}
+
+__device__ __forceinline__ void i8_update_chunk(const RepView &v, int x, int y, int j, int parity,
+                                                const uint64_t *sthr, Acc &a)
+{
+    const int Lx = v.Lx, Ly = v.Ly, C = v.C, Lz = v.Lz;
+    const uint32_t Lzp = v.Lzp;
+    uint8_t *sp = v.spins;
+    const uint32_t row = (uint32_t)x * (uint32_t)Ly + (uint32_t)y;
+    const uint32_t rowoff = row * Lzp;
+    const uint32_t jo = 8u * (uint32_t)j;
+    const uint32_t off = rowoff + jo;
+    const int q = (parity + x + y) & 1;
+    const bool last = (j == C - 1);
+    const int r = last ? (Lz - 8 * (C - 1)) : 8;
+
+    // neighbour rows; a missing x neighbour (free surface) reads the own
+    // chunk and is masked out, a seam neighbour is inverted when eps = -1
+    const uint32_t xs = v.seam_reflect ? (uint32_t)(Lx - 1 - x) : (uint32_t)x;
+    const uint64_t seam_mask = v.seam_invert ? kOnes8 : 0ull;
+    const bool ytop = (y == Ly - 1), ybot = (y == 0);
+    const uint32_t rp = ytop ? xs * (uint32_t)Ly : row + 1u;
+    const uint32_t rm = ybot ? xs * (uint32_t)Ly + (uint32_t)(Ly - 1) : row - 1u;
+    const uint64_t inv_p = ytop ? seam_mask : 0ull;
+    const uint64_t inv_m = ybot ? seam_mask : 0ull;
+    const uint32_t xstride = (uint32_t)Ly * Lzp;
+    const bool has_xm = x > 0, has_xp = x < Lx - 1;
+    const uint32_t oxm = has_xm ? off - xstride : off;
+    const uint32_t oxp = has_xp ? off + xstride : off;
+    const uint32_t oprev = (j > 0) ? off - 1u : rowoff + (uint32_t)(Lz - 1);
+    const uint32_t onext = last ? rowoff : off + 8u;
+
+    const uint64_t W = ld64(sp, off);
+    const uint64_t Yp = ld64(sp, rp * Lzp + jo);
+    const uint64_t Ym = ld64(sp, rm * Lzp + jo);
+    const uint64_t Xm = ld64(sp, oxm);
+    const uint64_t Xp = ld64(sp, oxp);
+    const uint64_t prev = ld8(sp, oprev);
+    const uint64_t next = ld8(sp, onext);
+
+    uint64_t cnt = ((W << 8) | prev) + ((W >> 8) | (next << (8 * (r - 1))));
+    cnt += (Yp ^ inv_p) + (Ym ^ inv_m);
+    cnt += (has_xm ? Xm : 0ull) + (has_xp ? Xp : 0ull);
+
+    const int cls = (x == 0 ? 1 : 0) + (x == Lx - 1 ? 2 : 0);
+    const int k = 6 - (x == 0) - (x == Lx - 1);
+    const uint64_t idxw = cnt + (W << 3);   // per byte: 8*u + count
+
+    const uint32_t g = ((row * (uint32_t)C + (uint32_t)j) << 1) | (uint32_t)q;
+    uint32_t rnd[4];
+    philox10(g, v.t, v.replica, 0u, v.key0, v.key1, rnd);
+
+    const uint64_t *tc = sthr + cls * kThrPerClass;
+    uint64_t flip = 0;
+#pragma unroll
+    for (int l = 0; l < 4; ++l) {
+        const int pos = q + 2 * l;
+        const uint32_t e = (uint32_t)(idxw >> (8 * pos)) & 0xFFu;
+        const uint64_t thr = tc[e];
+        flip |= (uint64_t)((uint64_t)rnd[l] < thr) << (8 * pos);
+    }
+    // sites past the end of a short last chunk are padding
+    const uint64_t valid = (r == 8) ? ~0ull : ((1ull << (8 * r)) - 1ull);
+    flip &= valid;
+    *(gu64 *)((gcu8 *)sp + off) = W ^ flip;
+
+    // dB = -2 sum_f s n with s = 2u-1, n = 2 cnt - k;  dM = sum_f (2 - 4u)
+    const uint64_t fu = flip & W;
+    const int nf = __popcll(flip), nfu = __popcll(fu);
+    const uint64_t fm = (flip << 8) - flip, fum = (fu << 8) - fu;
+    const int Sf = (int)bytesum64(cnt & fm), Sfu = (int)bytesum64(cnt & fum);
+    a.dB += -2 * (4 * Sfu - 2 * k * nfu - 2 * Sf + k * nf);
+    const int dm = 2 * nf - 4 * nfu;
+    a.dM += dm;
+    if (x == 0) a.dM1 += dm;
+    if (x == Lx - 1) a.dMn += dm;
+}
+
+// ---------------------------------------------------------------------------
+// bit-packed format: update one 32-bit word (32 same-phase sites).
+// Row layout: words [0, Wq) hold even z (z = 2i), words [Wq, 2Wq) odd z.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ uint32_t bp_bit(const uint32_t *sub, int i)
+{
+    return (sub[i >> 5] >> (i & 31)) & 1u;
+}
+
+__device__ __forceinline__ void bp_update_word(const RepView &v, int x, int y, int w, int parity,
+                                               const uint64_t *sthr, Acc &a)
+{
+    const int Lx = v.Lx, Ly = v.Ly, C = v.C, Wq = v.Wq;
+    const int nbits = v.Lz >> 1;
+    const uint32_t RW = 2u * (uint32_t)Wq;
+    const uint32_t row = (uint32_t)x * (uint32_t)Ly + (uint32_t)y;
+    uint32_t *words = (uint32_t *)v.spins;
+    const int q = (parity + x + y) & 1;
+    const uint32_t own = row * RW + (uint32_t)(q * Wq);
+    const uint32_t oth = row * RW + (uint32_t)((q ^ 1) * Wq);
+    const int nb_here = min(32, nbits - 32 * w);
+    const uint32_t vmask = nb_here >= 32 ? 0xFFFFFFFFu : ((1u << nb_here) - 1u);
+
+    const uint32_t S = words[own + w];
+    uint32_t zm, zp;
+    if (q == 0) {
+        // z = 2i: z+1 is odd index i, z-1 is odd index i-1
+        const uint32_t O = words[oth + w];
+        zp = O;
+        const uint32_t carry = (w > 0) ? (words[oth + w - 1] >> 31) : bp_bit(words + oth, nbits - 1);
+        zm = (O << 1) | carry;
+    } else {
+        // z = 2i+1: z-1 is even index i, z+1 is even index i+1
+        const uint32_t E = words[oth + w];
+        zm = E;
+        const bool lastw = (w == Wq - 1);
+        const uint32_t inb = words[oth + (lastw ? 0 : w + 1)] & 1u;
+        zp = (E >> 1) | (inb << (lastw ? (nb_here - 1) : 31));
+    }
+
+    const uint32_t xs = v.seam_reflect ? (uint32_t)(Lx - 1 - x) : (uint32_t)x;
+    const uint32_t seam_mask = v.seam_invert ? 0xFFFFFFFFu : 0u;
+    const uint32_t qo = (uint32_t)(q * Wq + w);
+    uint32_t yp, ym;
+    if (y < Ly - 1) yp = words[(row + 1) * RW + qo];
+    else yp = words[(xs * (uint32_t)Ly) * RW + qo] ^ seam_mask;
+    if (y > 0) ym = words[(row - 1) * RW + qo];
+    else ym = words[(xs * (uint32_t)Ly + (uint32_t)(Ly - 1)) * RW + qo] ^ seam_mask;
+    const uint32_t xstride = (uint32_t)Ly * RW;
+    const uint32_t xm = (x > 0) ? words[own + w - xstride] : 0u;
+    const uint32_t xp = (x < Lx - 1) ? words[own + w + xstride] : 0u;
+
+    // bit-sliced count of the six neighbour bits
+    const uint32_t s1 = zm ^ zp ^ ym, c1 = (zm & zp) | (ym & (zm ^ zp));
+    const uint32_t s2 = yp ^ xm ^ xp, c2 = (yp & xm) | (xp & (yp ^ xm));
+    const uint32_t b0 = s1 ^ s2, k0 = s1 & s2;
+    const uint32_t b1 = c1 ^ c2 ^ k0, b2 = (c1 & c2) | (k0 & (c1 ^ c2));
+
+    const int cls = (x == 0 ? 1 : 0) + (x == Lx - 1 ? 2 : 0);
+    const int k = 6 - (x == 0) - (x == Lx - 1);
+    const uint64_t *tc = sthr + cls * kThrPerClass;
+    const uint32_t gbase = row * (uint32_t)C + 8u * (uint32_t)w;
+    uint32_t F = 0;
+#pragma unroll
+    for (int g4 = 0; g4 < 8; ++g4) {
+        uint32_t rnd[4];
+        philox10(((gbase + g4) << 1) | (uint32_t)q, v.t, v.replica, 0u, v.key0, v.key1, rnd);
+#pragma unroll
+        for (int l = 0; l < 4; ++l) {
+            const int b = 4 * g4 + l;
+            const uint32_t e = ((S >> b) & 1u) << 3 | ((b2 >> b) & 1u) << 2 | ((b1 >> b) & 1u) << 1 |
+                               ((b0 >> b) & 1u);
+            F |= (uint32_t)((uint64_t)rnd[l] < tc[e]) << b;
+        }
+    }
+    F &= vmask;
+    words[own + w] = S ^ F;
+
+    const uint32_t FU = F & S;
+    const int nf = __popc(F), nfu = __popc(FU);
+    const int Sf = __popc(F & b0) + 2 * __popc(F & b1) + 4 * __popc(F & b2);
+    const int Sfu = __popc(FU & b0) + 2 * __popc(FU & b1) + 4 * __popc(FU & b2);
+    a.dB += -2 * (4 * Sfu - 2 * k * nfu - 2 * Sf + k * nf);
+    const int dm = 2 * nf - 4 * nfu;
+    a.dM += dm;
+    if (x == 0) a.dM1 += dm;
+    if (x == Lx - 1) a.dMn += dm;
+}
+
+// ---------------------------------------------------------------------------
+// int8 format, main phases (rows y >= 1): a thread owns one chunk column
+// (x0..x1-1, y, j) of its tile and marches through the x planes.  The chunk of
+// plane x-1 (read before its update: only the other-parity bytes are used,
+// and those are not written in this phase) and of plane x+1 stay in
+// registers, so a step loads the next plane, the two y neighbours and the two
+// z-edge bytes.  The per-byte table index 4*(cnt + 8u + 16*class) is formed
+// with word-wide adds; a shift by 8q moves the four sites of the phase to
+// bytes 0, 2, 4, 6.  A flip adds its packed (dB, dM) change to a register sum.
+// ---------------------------------------------------------------------------
+struct MarchLane {
+    uint32_t oc, oym, oprev, onext;   // offsets inside the current x plane
+    uint32_t dyp;                     // change per x step of the y+1 neighbour's offset
+    uint64_t inv_p;                   // seam sign of the y+1 neighbour
+    uint64_t valid, padidx;           // short last chunk: real bytes / padding index
+    int r;
+};
+
+// Neighbour data of one x step, loaded one step ahead of its use.
+struct StepIn {
+    uint64_t Wn, Yp, Ym;
+    uint32_t pb, nb;
+};
+
+__device__ __forceinline__ StepIn load_step(const RepView &v, const MarchLane &L, const gcu8 *base, int x,
+                                            uint32_t oyp, uint32_t xstride)
+{
+    StepIn in;
+    in.Wn = (x + 1 < v.Lx) ? *(gcu64 *)(base + xstride + L.oc) : 0ull;
+    in.Yp = ld64(v.spins, oyp) ^ L.inv_p;
+    in.Ym = *(gcu64 *)(base + L.oym);
+    in.pb = *(base + L.oprev);
+    in.nb = *(base + L.onext);
+    return in;
+}
+
+// int8 format, main phases (rows y >= 1): a thread owns one chunk column
+// (x0..x1-1, y, j) of its tile and marches through the x planes.  The chunk of
+// plane x-1 (read before its update: only its other-parity bytes are used,
+// and those are not written in this phase) and of plane x+1 stay in
+// registers; the y neighbours, the z-edge bytes and the next plane are loaded
+// one step ahead (none of them is written by this thread's current step, and
+// the bytes used are not written in this phase at all).  The per-byte table
+// index 4*(cnt + 8u + 16*class) is formed with word-wide adds; a shift by 8q
+// moves the four sites of the phase to bytes 0, 2, 4, 6.  A flip adds its
+// packed (dB, dM) change to a register sum.
+template <bool NEVER, bool RAGGED>
+__device__ __forceinline__ void i8_march(const RepView &v, const Entry &en, int parity, const Tables *tb, Acc &a)
+{
+    const int tid = threadIdx.x;
+    const int ty = tid / v.tj;
+    const int tj = tid - ty * v.tj;
+    const int y = en.y0 + ty;
+    const int j = en.j0 + tj;
+    if (ty >= v.ty || y >= v.Ly || j >= v.C) return;
+    const int Lx = v.Lx, Ly = v.Ly, C = v.C, Lz = v.Lz;
+    const uint32_t Lzp = v.Lzp;
+    const int x0 = en.x0;
+    const int x1 = min(en.x0 + v.mx, Lx);
+    const uint32_t xstride = (uint32_t)Ly * Lzp;
+    const uint32_t jo = 8u * (uint32_t)j;
+    const bool last = (j == C - 1);
+
+    MarchLane L;
+    L.r = last ? (Lz - 8 * (C - 1)) : 8;
+    const uint32_t yrow = (uint32_t)y * Lzp;
+    L.oc = yrow + jo;
+    L.oym = L.oc - Lzp;
+    L.oprev = (j > 0) ? L.oc - 1u : yrow + (uint32_t)(Lz - 1);
+    L.onext = last ? yrow : L.oc + 8u;
+    L.inv_p = 0;
+    uint32_t oyp;
+    if (y < Ly - 1) {
+        oyp = (uint32_t)x0 * xstride + L.oc + Lzp;
+        L.dyp = xstride;
+    } else {
+        const uint32_t xs0 = v.seam_reflect ? (uint32_t)(Lx - 1 - x0) : (uint32_t)x0;
+        oyp = xs0 * xstride + jo;
+        L.dyp = v.seam_reflect ? (uint32_t)(0u - xstride) : xstride;
+        L.inv_p = v.seam_invert ? kOnes8 : 0ull;
+    }
+    L.valid = (L.r == 8) ? ~0ull : ((1ull << (8 * L.r)) - 1ull);
+    L.padidx = ~L.valid & (0x0101010101010101ull * (uint64_t)(4 * kPadEntry));
+
+    const gcu8 *base = (gcu8 *)v.spins + (size_t)x0 * xstride;
+    const uint32_t gstep = 2u * (uint32_t)Ly * (uint32_t)C;
+    int q = (parity + x0 + y) & 1;
+    uint32_t g = ((((uint32_t)x0 * (uint32_t)Ly + (uint32_t)y) * (uint32_t)C + (uint32_t)j) << 1) | (uint32_t)q;
+
+    uint64_t Wc = *(gcu64 *)(base + L.oc);
+    uint64_t Wm = (x0 > 0) ? *(gcu64 *)(base - xstride + L.oc) : 0ull;
+    StepIn cur = load_step(v, L, base, x0, oyp, xstride);
+    int dsum = 0, d1 = 0, dn = 0;
+    for (int x = x0; x < x1; ++x) {
+        // next step's neighbours first: independent of this step's result
+        StepIn nxt;
+        const bool more = x + 1 < x1;
+        if (more) nxt = load_step(v, L, base + xstride, x + 1, oyp + L.dyp, xstride);
+        uint64_t cnt = ((Wc << 8) | (uint64_t)cur.pb) + ((Wc >> 8) | ((uint64_t)cur.nb << (8 * (L.r - 1))));
+        cnt += cur.Yp + cur.Ym;
+        cnt += Wm + cur.Wn;
+        const uint64_t clsw =
+            (x == 0 ? 0x4040404040404040ull : 0ull) + (x == Lx - 1 ? 0x8080808080808080ull : 0ull);
+        uint64_t idx = (cnt << 2) + (Wc << 5) + clsw;
+        if (RAGGED) idx = (idx & L.valid) | L.padidx;
+        idx >>= 8 * q;
+        uint32_t rnd[4];
+        philox10(g, v.t, v.replica, 0u, v.key0, v.key1, rnd);
+        const uint32_t ilo = (uint32_t)idx, ihi = (uint32_t)(idx >> 32);
+        const uint32_t e[4] = {(ilo & 0xFFu) >> 2, (ilo >> 18) & 0x3Fu, (ihi & 0xFFu) >> 2, (ihi >> 18) & 0x3Fu};
+        bool acc[4];
+        int dp[4];
+#pragma unroll
+        for (int l = 0; l < 4; ++l) {
+            const TD t = tb->td[e[l]];
+            if (NEVER) acc[l] = (uint64_t)rnd[l] < tb->thr[e[l]];
+            else acc[l] = rnd[l] <= t.thr_m1;
+            dp[l] = acc[l] ? t.dpack : 0;
+        }
+        const int step = (dp[0] + dp[1]) + (dp[2] + dp[3]);
+        const uint32_t flo = (acc[0] ? 1u : 0u) | (acc[1] ? 0x10000u : 0u);
+        const uint32_t fhi = (acc[2] ? 1u : 0u) | (acc[3] ? 0x10000u : 0u);
+        uint64_t flip = ((uint64_t)fhi << 32 | flo) << (8 * q);
+        if (RAGGED) flip &= L.valid;
+        *(gu64 *)((gcu8 *)base + L.oc) = Wc ^ flip;
+        dsum += step;
+        if (x == 0) d1 += step;
+        if (x == Lx - 1) dn += step;
+        Wm = Wc;
+        Wc = cur.Wn;
+        if (more) cur = nxt;
+        base += xstride;
+        oyp += L.dyp;
+        g += gstep;
+        g ^= 1u;
+        q ^= 1;
+    }
+    // packed sums: dB in the low 16 bits (|sum| < 2^15 for <= kMaxMarch planes)
+    const int dB = (int)(int16_t)(dsum & 0xFFFF), dM = (dsum - dB) >> 16;
+    a.dB += dB;
+    a.dM += dM;
+    const int dB1 = (int)(int16_t)(d1 & 0xFFFF), dBn = (int)(int16_t)(dn & 0xFFFF);
+    a.dM1 += (d1 - dB1) >> 16;
+    a.dMn += (dn - dBn) >> 16;
+}
+
+// ---------------------------------------------------------------------------
+// Processing of a contiguous range of work entries by one workgroup.
+// ---------------------------------------------------------------------------
+template <int FMT, bool SEAM>
+__device__ __forceinline__ void process_range(const RepDesc *__restrict__ descs,
+                                              const RepState *__restrict__ st,
+                                              const Entry *__restrict__ work, long e0, long e1, int parity,
+                                              uint32_t t_offset, Tables *tb)
+{
+    const bool seam = SEAM;
+    Acc a = {0, 0, 0, 0};
+    int cur_rep = -1;
+    RepView v;
+    for (long e = e0; e < e1; ++e) {
+        const Entry en = work[e];
+        if (en.rep != cur_rep) {
+            if (cur_rep >= 0) flush_acc(a, v.acc, v.t, blockIdx.x & (kAccSlots - 1));
+            cur_rep = en.rep;
+            v = load_view(descs, st, cur_rep, seam, t_offset);
+            load_tables(descs[cur_rep], tb);
+            __syncthreads();
+        }
+        if (FMT == ISLF_SPIN_INT8 && !seam) {
+            const bool ragged = (v.Lz & 7) != 0;
+            if (v.never) {
+                if (ragged) i8_march<true, true>(v, en, parity, tb, a);
+                else i8_march<true, false>(v, en, parity, tb, a);
+            } else {
+                if (ragged) i8_march<false, true>(v, en, parity, tb, a);
+                else i8_march<false, false>(v, en, parity, tb, a);
+            }
+            continue;
+        }
+        const int tid = threadIdx.x;
+        const int j = en.j0 + (tid & ((1 << v.lj) - 1));
+        const int y = en.y0 + ((tid >> v.lj) & ((1 << v.ly) - 1));
+        const int x = en.x0 + (tid >> (v.lj + v.ly));
+        const int jmax = (FMT == ISLF_SPIN_INT8) ? v.C : v.Wq;
+        const bool inside = (x < v.Lx) && (j < jmax) && (seam ? (y == 0) : (y < v.Ly));
+        if (inside) {
+            if (FMT == ISLF_SPIN_INT8) i8_update_chunk(v, x, y, j, parity, tb->thr, a);
+            else bp_update_word(v, x, y, j, parity, tb->thr, a);
+        }
+    }
+    if (cur_rep >= 0) flush_acc(a, v.acc, v.t, blockIdx.x & (kAccSlots - 1));
+}
+
+// One phase of one sweep over the entries [0, n_entries): block b takes the
+// contiguous range [b*n/G, (b+1)*n/G).
+template <int FMT, bool SEAM>
+__global__ __launch_bounds__(kBlock) void k_phase(const RepDesc *__restrict__ descs,
+                                                  const RepState *__restrict__ st,
+                                                  const Entry *__restrict__ work, long n_entries,
+                                                  int phase)
+{
+    __shared__ Tables tb;
+    const long G = gridDim.x;
+    const long e0 = (long)blockIdx.x * n_entries / G;
+    const long e1 = (long)(blockIdx.x + 1) * n_entries / G;
+    process_range<FMT, SEAM>(descs, st, work, e0, e1, phase & 1, 0u, &tb);
+}
+
+// End of a sweep: fold the spread partial sums into the running observables,
+// store the record of sweep t, clear the accumulator and advance t.
+// One wave per listed replica.
+__global__ void k_end_sweep(const RepDesc *__restrict__ descs, RepState *__restrict__ st,
+                            const int *__restrict__ reps, int n)
+{
+    const int wave = (blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+    const int lane = threadIdx.x & 63;
+    if (wave >= n) return;
+    const int r = reps[wave];
+    const RepDesc &d = descs[r];
+    const uint32_t t = st[r].t;
+    long long *slot = d.acc + ((size_t)(t & 1) * kAccSlots + lane) * 4;
+    long long v[4];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        v[k] = slot[k];
+        slot[k] = 0;
+    }
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+#pragma unroll
+        for (int off = 32; off > 0; off >>= 1) v[k] += __shfl_xor(v[k], off, 64);
+    }
+    if (lane == 0) {
+        RepState &s = st[r];
+        islf_obs o;
+        o.B = s.cur[0] + v[0];
+        o.M = s.cur[1] + v[1];
+        o.M1 = s.cur[2] + v[2];
+        o.Mn = s.cur[3] + v[3];
+        s.cur[0] = o.B; s.cur[1] = o.M; s.cur[2] = o.M1; s.cur[3] = o.Mn;
+        d.rec[t % d.cap] = o;
+        s.t = t + 1;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Persistent form: all sweeps of all replicas in one launch; phases are
+// separated by a grid-wide barrier with a bounded wait.
+// ---------------------------------------------------------------------------
+// Barrier number k of a launch completes when the monotonic arrival counter
+// reaches (k+1) * nblocks.  Only atomic read-modify-writes touch the counter
+// (the host re-zeroes it with a fill kernel before each launch), and the
+// wait is bounded: on time-out the error word is set and the kernel ends.
+__device__ bool grid_barrier(GridSync *sync, unsigned long long nblocks, unsigned long long &passed)
+{
+    __syncthreads();
+    __shared__ int ok;
+    if (threadIdx.x == 0) {
+        ok = 1;
+        const unsigned long long target = (passed + 1) * nblocks;
+        __threadfence();
+        atomicAdd(&sync->count, 1ull);
+        unsigned long spins = 0;
+        while (__hip_atomic_load(&sync->count, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) < target) {
+            __builtin_amdgcn_s_sleep(1);
+            if (++spins > (1ul << 22) ||
+                __hip_atomic_load(&sync->error, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) {
+                atomicOr(&sync->error, 1u);
+                ok = 0;
+                break;
+            }
+        }
+        __threadfence();
+    }
+    passed += 1;
+    __syncthreads();
+    return ok != 0;
+}
+
+template <int FMT>
+__global__ __launch_bounds__(kBlock) void k_persistent(const RepDesc *__restrict__ descs,
+                                                       RepState *__restrict__ st,
+                                                       const Entry *__restrict__ work_main, long n_main,
+                                                       const Entry *__restrict__ work_seam, long n_seam,
+                                                       const int *__restrict__ reps, int n_reps,
+                                                       uint32_t n_sweeps, GridSync *sync)
+{
+    __shared__ Tables tb;
+    const long G = gridDim.x;
+    const long b = blockIdx.x;
+    unsigned long long passed = 0;
+    for (uint32_t s = 0; s < n_sweeps; ++s) {
+        for (int p = 0; p < 4; ++p) {
+            if (p >= 2) process_range<FMT, true>(descs, st, work_seam, b * n_seam / G, (b + 1) * n_seam / G, p & 1, s, &tb);
+            else process_range<FMT, false>(descs, st, work_main, b * n_main / G, (b + 1) * n_main / G, p & 1, s, &tb);
+            if (!grid_barrier(sync, (unsigned long long)G, passed)) return;
+        }
+        // bookkeeping of sweep s: replica i is folded by block i mod G while
+        // the other blocks go on with the next sweep (other accumulator half)
+        for (int i = (int)b; i < n_reps; i += (int)G) {
+            if (threadIdx.x < 64) {
+                const int lane = threadIdx.x;
+                const int r = reps[i];
+                const RepDesc &d = descs[r];
+                const uint32_t t = st[r].t + s;
+                long long *slot = d.acc + ((size_t)(t & 1) * kAccSlots + lane) * 4;
+                long long v[4];
+#pragma unroll
+                for (int k = 0; k < 4; ++k)
+                    v[k] = (long long)atomicExch((unsigned long long *)&slot[k], 0ull);
+#pragma unroll
+                for (int k = 0; k < 4; ++k) {
+#pragma unroll
+                    for (int off = 32; off > 0; off >>= 1) v[k] += __shfl_xor(v[k], off, 64);
+                }
+                if (lane == 0) {
+                    RepState &sr = st[r];
+                    islf_obs o;
+                    o.B = sr.cur[0] + v[0];
+                    o.M = sr.cur[1] + v[1];
+                    o.M1 = sr.cur[2] + v[2];
+                    o.Mn = sr.cur[3] + v[3];
+                    sr.cur[0] = o.B; sr.cur[1] = o.M; sr.cur[2] = o.M1; sr.cur[3] = o.Mn;
+                    d.rec[t % d.cap] = o;
+                }
+            }
+        }
+    }
+    // every block has passed the last barrier: advance the sweep counters
+    if (!grid_barrier(sync, (unsigned long long)G, passed)) return;
+    for (int i = (int)b * kBlock + threadIdx.x; i < n_reps; i += (int)G * kBlock) st[reps[i]].t += n_sweeps;
+}
+
+// ---------------------------------------------------------------------------
+// Initial states and format conversion.
+// mode 0: random (Philox domain 1, t = 0; +1 iff the word's top bit is 0),
+// mode 1: all up, 2: all down, 3: from staged host spins (int8 +-1, host layout).
+// ---------------------------------------------------------------------------
+__global__ void k_init_i8(const RepDesc *__restrict__ descs, int rep, int mode, const int8_t *__restrict__ host)
+{
+    const RepDesc &d = descs[rep];
+    const long nch = (long)d.Lx * d.Ly * d.C;
+    for (long k = (long)blockIdx.x * blockDim.x + threadIdx.x; k < nch; k += (long)gridDim.x * blockDim.x) {
+        const long row = k / d.C;
+        const int j = (int)(k - row * d.C);
+        const int r = (j == d.C - 1) ? d.Lz - 8 * (d.C - 1) : 8;
+        uint64_t W = 0;
+        if (mode == 0) {
+            for (int q = 0; q < 2; ++q) {
+                uint32_t rnd[4];
+                philox10((((uint32_t)k) << 1) | (uint32_t)q, 0u, d.replica, 1u, d.key0, d.key1, rnd);
+                for (int l = 0; l < 4; ++l) {
+                    const int pos = q + 2 * l;
+                    if (pos < r) W |= (uint64_t)(1u - (rnd[l] >> 31)) << (8 * pos);
+                }
+            }
+        } else if (mode == 1) {
+            for (int pos = 0; pos < r; ++pos) W |= 1ull << (8 * pos);
+        } else if (mode == 3) {
+            const int8_t *src = host + row * d.Lz + 8 * j;
+            for (int pos = 0; pos < r; ++pos) W |= (uint64_t)(src[pos] > 0 ? 1u : 0u) << (8 * pos);
+        }
+        *(uint64_t *)(d.spins + (size_t)row * d.Lzp + 8 * j) = W;
+    }
+}
+
+__global__ void k_init_bp(const RepDesc *__restrict__ descs, int rep, int mode, const int8_t *__restrict__ host)
+{
+    const RepDesc &d = descs[rep];
+    const int nbits = d.Lz >> 1;
+    const long nw = (long)d.Lx * d.Ly * 2 * d.Wq;
+    uint32_t *words = (uint32_t *)d.spins;
+    for (long k = (long)blockIdx.x * blockDim.x + threadIdx.x; k < nw; k += (long)gridDim.x * blockDim.x) {
+        const long row = k / (2 * d.Wq);
+        const int rem = (int)(k - row * 2 * d.Wq);
+        const int q = rem / d.Wq, w = rem - q * d.Wq;
+        const int nb_here = min(32, nbits - 32 * w);
+        uint32_t S = 0;
+        for (int b = 0; b < nb_here; ++b) {
+            const int i = 32 * w + b;
+            uint32_t u;
+            if (mode == 0) {
+                uint32_t rnd[4];
+                const uint32_t g = (((uint32_t)(row * d.C + (i >> 2))) << 1) | (uint32_t)q;
+                philox10(g, 0u, d.replica, 1u, d.key0, d.key1, rnd);
+                u = 1u - (rnd[i & 3] >> 31);
+            } else if (mode == 1) {
+                u = 1;
+            } else if (mode == 2) {
+                u = 0;
+            } else {
+                u = host[row * d.Lz + 2 * i + q] > 0 ? 1u : 0u;
+            }
+            S |= u << b;
+        }
+        words[k] = S;
+    }
+}
+
+// Internal format -> host layout int8 +-1.
+__global__ void k_export(const RepDesc *__restrict__ descs, int rep, int8_t *__restrict__ out)
+{
+    const RepDesc &d = descs[rep];
+    const long N = (long)d.Lx * d.Ly * d.Lz;
+    for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < N; i += (long)gridDim.x * blockDim.x) {
+        const long row = i / d.Lz;
+        const int z = (int)(i - row * d.Lz);
+        uint32_t u;
+        if (d.fmt == ISLF_SPIN_INT8) {
+            u = d.spins[(size_t)row * d.Lzp + z];
+        } else {
+            const uint32_t *sub = (const uint32_t *)d.spins + (size_t)row * 2 * d.Wq + (size_t)(z & 1) * d.Wq;
+            u = bp_bit(sub, z >> 1);
+        }
+        out[i] = u ? (int8_t)1 : (int8_t)-1;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Full recompute of (B, M, M1, Mn): each site counts its three forward slots.
+// Works on the host-layout export so that it is one code for both formats.
+// ---------------------------------------------------------------------------
+__global__ void k_recompute(const RepDesc *__restrict__ descs, int rep, const int8_t *__restrict__ s,
+                            unsigned long long *__restrict__ out)
+{
+    const RepDesc &d = descs[rep];
+    const int Lx = d.Lx, Ly = d.Ly, Lz = d.Lz;
+    const long N = (long)Lx * Ly * Lz;
+    long long B = 0, M = 0, M1 = 0, Mn = 0;
+    for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < N; i += (long)gridDim.x * blockDim.x) {
+        const int z = (int)(i % Lz);
+        const long row = i / Lz;
+        const int y = (int)(row % Ly);
+        const int x = (int)(row / Ly);
+        const int si = s[i];
+        if (x < Lx - 1) B += si * s[i + (long)Ly * Lz];
+        B += si * s[row * Lz + (z + 1 == Lz ? 0 : z + 1)];
+        if (y < Ly - 1) {
+            B += si * s[i + Lz];
+        } else {
+            const int xs = d.seam_reflect ? Lx - 1 - x : x;
+            const int sg = d.seam_invert ? -1 : 1;
+            B += sg * si * s[((long)xs * Ly) * Lz + z];
+        }
+        M += si;
+        if (x == 0) M1 += si;
+        if (x == Lx - 1) Mn += si;
+    }
+    long long v[4] = {B, M, M1, Mn};
+    __shared__ long long red[4][kBlock / 64];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+#pragma unroll
+        for (int off = 32; off > 0; off >>= 1) v[k] += __shfl_xor(v[k], off, 64);
+    }
+    if ((threadIdx.x & 63) == 0) {
+        for (int k = 0; k < 4; ++k) red[k][threadIdx.x >> 6] = v[k];
+    }
+    __syncthreads();
+    if (threadIdx.x < 4) {
+        long long acc = 0;
+        for (int w = 0; w < (int)(blockDim.x >> 6); ++w) acc += red[threadIdx.x][w];
+        atomicAdd(&out[threadIdx.x], (unsigned long long)acc);
+    }
+}
+
+// Sets the running observables of a replica (after init / set_spins).
+__global__ void k_set_state(RepState *st, int rep, const unsigned long long *obs, uint32_t t)
+{
+    if (threadIdx.x == 0 && blockIdx.x == 0) {
+        for (int k = 0; k < 4; ++k) st[rep].cur[k] = (long long)obs[k];
+        st[rep].t = t;
+        st[rep].live = 1;
+    }
+}
+
+__global__ void k_zero_u64(unsigned long long *p, long n)
+{
+    for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long)gridDim.x * blockDim.x) p[i] = 0;
+}
+
+// ---------------------------------------------------------------------------
+// Energies and means (Eq. 1, Eq. 19 integrand); thermodynamic integration.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ double energy_of(double J, double H, double h1, double hn, double B, double M,
+                                            double M1, double Mn)
+{
+    double e = -J * B;
+    e = e - H * M;
+    e = e - h1 * M1;
+    e = e - hn * Mn;
+    return e;
+}
+
+__global__ void k_energy(const islf_obs *__restrict__ rec, uint32_t cap, uint64_t first, uint32_t count,
+                         double J, double H, double h1, double hn, double *__restrict__ out)
+{
+    for (uint32_t k = blockIdx.x * blockDim.x + threadIdx.x; k < count; k += gridDim.x * blockDim.x) {
+        const islf_obs o = rec[(first + k) % cap];
+        out[k] = energy_of(J, H, h1, hn, (double)o.B, (double)o.M, (double)o.M1, (double)o.Mn);
+    }
+}
+
+// One block per replica: exact int64 sums of the records, then
+// mean = (double)sum / (double)count; mean E from the means.
+__global__ void k_means(const RepDesc *__restrict__ descs, const int *__restrict__ reps, uint64_t first, uint32_t count, double *__restrict__ out)
+{
+    const int i = blockIdx.x;
+    const int r = reps[i];
+    const RepDesc &d = descs[r];
+    long long v[4] = {0, 0, 0, 0};
+    for (uint32_t k = threadIdx.x; k < count; k += blockDim.x) {
+        const islf_obs o = d.rec[(first + k) % d.cap];
+        v[0] += o.B; v[1] += o.M; v[2] += o.M1; v[3] += o.Mn;
+    }
+    __shared__ long long red[4][kBlock / 64];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+#pragma unroll
+        for (int off = 32; off > 0; off >>= 1) v[k] += __shfl_xor(v[k], off, 64);
+    }
+    if ((threadIdx.x & 63) == 0) {
+        for (int k = 0; k < 4; ++k) red[k][threadIdx.x >> 6] = v[k];
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double m[4];
+        for (int k = 0; k < 4; ++k) {
+            long long s = 0;
+            for (int w = 0; w < (int)(blockDim.x >> 6); ++w) s += red[k][w];
+            m[k] = (double)s / (double)count;
+        }
+        out[5 * (size_t)i + 0] = energy_of(d.J, d.H, d.h1, d.hn, m[0], m[1], m[2], m[3]);
+        for (int k = 0; k < 4; ++k) out[5 * (size_t)i + 1 + k] = m[k];
+    }
+}
+
+__global__ void k_integrate(const double *__restrict__ h, const double *__restrict__ m1,
+                            const double *__restrict__ mn, int n, double c1, double cn, double norm,
+                            double *__restrict__ out)
+{
+    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+    double g_prev = norm * (c1 * m1[0] + cn * mn[0]);
+    double acc = 0.0;
+    out[0] = 0.0;
+    for (int r = 1; r < n; ++r) {
+        const double g = norm * (c1 * m1[r] + cn * mn[r]);
+        const double step = 0.5 * (h[r] - h[r - 1]);
+        acc = acc + step * (g_prev + g);
+        out[r] = acc;
+        g_prev = g;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Host-callable launchers (used by islf_api.hip).
+// ---------------------------------------------------------------------------
+hipError_t launch_phase(int fmt, const RepDesc *descs, const RepState *st, const Entry *work, long n,
+                        int phase, int grid, hipStream_t s)
+{
+    if (n <= 0) return hipSuccess;
+    if (grid > n) grid = (int)n;
+    const bool seam = phase >= 2;
+    if (fmt == ISLF_SPIN_INT8) {
+        if (seam) hipLaunchKernelGGL((k_phase<ISLF_SPIN_INT8, true>), dim3(grid), dim3(kBlock), 0, s, descs, st, work, n, phase);
+        else hipLaunchKernelGGL((k_phase<ISLF_SPIN_INT8, false>), dim3(grid), dim3(kBlock), 0, s, descs, st, work, n, phase);
+    } else {
+        if (seam) hipLaunchKernelGGL((k_phase<ISLF_SPIN_BITPACK, true>), dim3(grid), dim3(kBlock), 0, s, descs, st, work, n, phase);
+        else hipLaunchKernelGGL((k_phase<ISLF_SPIN_BITPACK, false>), dim3(grid), dim3(kBlock), 0, s, descs, st, work, n, phase);
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_end_sweep(const RepDesc *descs, RepState *st, const int *reps, int n, hipStream_t s)
+{
+    if (n <= 0) return hipSuccess;
+    const int blocks = (n * 64 + kBlock - 1) / kBlock;
+    hipLaunchKernelGGL(k_end_sweep, dim3(blocks), dim3(kBlock), 0, s, descs, st, reps, n);
+    return hipGetLastError();
+}
+
+const void *persistent_kernel(int fmt)
+{
+    return fmt == ISLF_SPIN_INT8 ? (const void *)k_persistent<ISLF_SPIN_INT8>
+                                 : (const void *)k_persistent<ISLF_SPIN_BITPACK>;
+}
+
+hipError_t launch_persistent(int fmt, const RepDesc *descs, RepState *st, const Entry *wm, long nm,
+                             const Entry *ws, long ns, const int *reps, int nreps, uint32_t nsweeps,
+                             GridSync *sync, int grid, hipStream_t s)
+{
+    void *args[] = {(void *)&descs, (void *)&st, (void *)&wm, (void *)&nm, (void *)&ws, (void *)&ns,
+                    (void *)&reps, (void *)&nreps, (void *)&nsweeps, (void *)&sync};
+    hipLaunchKernelGGL(k_zero_u64, dim3(1), dim3(64), 0, s, (unsigned long long *)&sync->count, 1L);
+    const hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    return hipLaunchCooperativeKernel(persistent_kernel(fmt), dim3(grid), dim3(kBlock), args, 0, s);
+}
+
+hipError_t launch_init(int fmt, const RepDesc *descs, int rep, int mode, const int8_t *host, hipStream_t s)
+{
+    if (fmt == ISLF_SPIN_INT8)
+        hipLaunchKernelGGL(k_init_i8, dim3(1024), dim3(kBlock), 0, s, descs, rep, mode, host);
+    else
+        hipLaunchKernelGGL(k_init_bp, dim3(1024), dim3(kBlock), 0, s, descs, rep, mode, host);
+    return hipGetLastError();
+}
+
+hipError_t launch_export(const RepDesc *descs, int rep, int8_t *out, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_export, dim3(1024), dim3(kBlock), 0, s, descs, rep, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_recompute(const RepDesc *descs, int rep, const int8_t *spins, unsigned long long *out,
+                            hipStream_t s)
+{
+    hipLaunchKernelGGL(k_zero_u64, dim3(1), dim3(64), 0, s, out, 4L);
+    hipLaunchKernelGGL(k_recompute, dim3(1024), dim3(kBlock), 0, s, descs, rep, spins, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_set_state(RepState *st, int rep, const unsigned long long *obs, uint32_t t, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_set_state, dim3(1), dim3(64), 0, s, st, rep, obs, t);
+    return hipGetLastError();
+}
+
+hipError_t launch_zero(unsigned long long *p, long n, hipStream_t s)
+{
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_zero_u64, dim3(256), dim3(kBlock), 0, s, p, n);
+    return hipGetLastError();
+}
+
+hipError_t launch_energy(const islf_obs *rec, uint32_t cap, uint64_t first, uint32_t count, double J,
+                         double H, double h1, double hn, double *out, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_energy, dim3(64), dim3(kBlock), 0, s, rec, cap, first, count, J, H, h1, hn, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_means(const RepDesc *descs, const int *reps, int n, uint64_t first, uint32_t count,
+                        double *out, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_means, dim3(n), dim3(kBlock), 0, s, descs, reps, first, count, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_integrate(const double *h, const double *m1, const double *mn, int n, double c1, double cn,
+                            double norm, double *out, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_integrate, dim3(1), dim3(64), 0, s, h, m1, mn, n, c1, cn, norm, out);
+    return hipGetLastError();
+}
+
+}  // namespace islf

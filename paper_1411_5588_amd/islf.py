@@ -1,0 +1,319 @@
+"""Python binding of libislf (include/islf.h): argument marshalling only.
+
+Every step of the Monte Carlo path runs in the library's HIP kernels on the
+GPU; this module converts Python values to the C ABI and back.  PyTorch
+supplies device memory (its caching allocator backs the library's
+allocations) and the HIP stream the work is issued on.
+
+Model and update rule: thin-film Ising model of arXiv:1411.5588 (Sec. II.A
+Eq. 1, y boundaries of Eq. 11), checkerboard Metropolis (Appendix), observables
+of Eq. 7 / Eq. 19, thermodynamic integration of Eq. 9 / Eq. 22.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+from dataclasses import dataclass, field
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libislf.so")
+
+OK, EINVAL, ENOMEM, EDEVICE, ESTATE, ERANGE = range(6)
+PBC, APBC, GAPBC = 0, 1, 2
+INT8, BITPACK = 0, 1
+INIT_RANDOM, INIT_UP, INIT_DOWN, INIT_HOST = 0, 1, 2, 3
+EXEC_PLAIN, EXEC_BATCHED, EXEC_PERSISTENT = 0, 1, 2
+
+_STATUS = {EINVAL: "EINVAL", ENOMEM: "ENOMEM", EDEVICE: "EDEVICE", ESTATE: "ESTATE", ERANGE: "ERANGE"}
+
+
+class IslfError(RuntimeError):
+    def __init__(self, status: int, message: str):
+        super().__init__(f"{_STATUS.get(status, status)}: {message}")
+        self.status = status
+
+
+class ReplicaDesc(C.Structure):
+    _fields_ = [("Lx", C.c_int32), ("Ly", C.c_int32), ("Lz", C.c_int32), ("ybc", C.c_int32),
+                ("J", C.c_double), ("beta", C.c_double), ("H", C.c_double), ("h1", C.c_double),
+                ("hn", C.c_double), ("seed", C.c_uint64), ("replica", C.c_uint32), ("init", C.c_int32)]
+
+
+class Obs(C.Structure):
+    _fields_ = [("B", C.c_int64), ("M", C.c_int64), ("M1", C.c_int64), ("Mn", C.c_int64)]
+
+
+@dataclass
+class Replica:
+    """Parameters of one Markov chain (Sec. II.A Eq. 1; h1 on x = 0, hn on x = Lx-1)."""
+    Lx: int
+    Ly: int
+    Lz: int
+    ybc: int = GAPBC
+    J: float = 1.0
+    beta: float = 1.0 / 3.0
+    H: float = 0.0
+    h1: float = 0.0
+    hn: float = 0.0
+    seed: int = 0
+    replica: int = 0
+    init: int = INIT_RANDOM
+
+    def to_c(self) -> ReplicaDesc:
+        return ReplicaDesc(self.Lx, self.Ly, self.Lz, self.ybc, self.J, self.beta, self.H, self.h1,
+                           self.hn, self.seed & (2**64 - 1), self.replica & (2**32 - 1), self.init)
+
+    @property
+    def N(self) -> int:
+        return self.Lx * self.Ly * self.Lz
+
+
+_ALLOC_FN = C.CFUNCTYPE(C.c_void_p, C.c_size_t, C.c_void_p)
+_FREE_FN = C.CFUNCTYPE(None, C.c_void_p, C.c_void_p)
+
+_lib = None
+
+
+def lib():
+    """Loads libislf.so; raises if the HIP library has not been built."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is missing: build it with `python -m paper_1411_5588_amd.build`")
+        L = C.CDLL(LIB_PATH)
+        vp, i32, u32, u64, i64, dbl, sz = C.c_void_p, C.c_int32, C.c_uint32, C.c_uint64, C.c_int64, C.c_double, C.c_size_t
+        P = C.POINTER
+        sig = {
+            "islf_create": [P(ReplicaDesc), i32, i32, u32, vp, P(vp)],
+            "islf_create_with_allocator": [P(ReplicaDesc), i32, i32, u32, vp, _ALLOC_FN, _FREE_FN, vp, P(vp)],
+            "islf_destroy": [vp],
+            "islf_num_replicas": [vp, P(i32)],
+            "islf_get_desc": [vp, i32, P(ReplicaDesc)],
+            "islf_set_spins": [vp, i32, vp, sz],
+            "islf_get_spins": [vp, i32, vp, sz],
+            "islf_set_exec": [vp, i32],
+            "islf_sweep": [vp, u32],
+            "islf_sweep_count": [vp, i32, P(u64)],
+            "islf_measure": [vp, i32, u64, u32, vp],
+            "islf_recompute": [vp, i32, P(Obs)],
+            "islf_energy": [vp, i32, u64, u32, vp],
+            "islf_means": [vp, u64, u32, vp],
+            "islf_integrate": [vp, vp, vp, i32, dbl, dbl, dbl, vp, vp],
+            "islf_footprint_bytes": [P(ReplicaDesc), i32, u32, P(u64)],
+            "islf_batch_add": [vp, P(ReplicaDesc), P(i32)],
+            "islf_batch_retire": [vp, i32],
+            "islf_graph_capture": [vp, u32],
+            "islf_run_graph": [vp, u32],
+            "islf_num_tiles": [i32, P(i32)],
+            "islf_get_tile": [vp, i32, P(i32)],
+            "islf_set_tile": [vp, i32, i32],
+            "islf_autotune": [vp, u32],
+        }
+        for name, args in sig.items():
+            f = getattr(L, name)
+            f.argtypes = args
+            f.restype = C.c_int
+        L.islf_last_error.restype = C.c_char_p
+        L.islf_last_error.argtypes = []
+        _lib = L
+    return _lib
+
+
+def _check(status: int):
+    if status != OK:
+        raise IslfError(status, lib().islf_last_error().decode(errors="replace"))
+
+
+def exported_symbols() -> list[str]:
+    return [n for n in dir(lib()) if n.startswith("islf_")]
+
+
+class _TorchAllocator:
+    """Routes the library's device allocations through torch's caching allocator."""
+
+    def __init__(self, torch, device, stream):
+        self.torch = torch
+        self.device = device
+        self.stream = stream
+
+        def _alloc(nbytes, user):
+            try:
+                return int(torch.cuda.caching_allocator_alloc(int(nbytes), device=self.device,
+                                                              stream=self.stream))
+            except Exception:  # out of memory: the library reports ENOMEM
+                return None
+
+        def _free(ptr, user):
+            if ptr:
+                torch.cuda.caching_allocator_delete(int(ptr))
+
+        self.alloc = _ALLOC_FN(_alloc)
+        self.free = _FREE_FN(_free)
+
+
+def _torch():
+    import torch
+    if not torch.cuda.is_available():
+        raise RuntimeError("no GPU: the islf path runs only on an MI355X (gfx950) device")
+    return torch
+
+
+class Context:
+    """A set of replicas on one GPU (islf_ctx)."""
+
+    def __init__(self, replicas, spin_format=INT8, obs_capacity=1024, stream=None, exec_mode=EXEC_BATCHED,
+                 torch_allocator=True):
+        torch = _torch()
+        self.torch = torch
+        # a stream of its own (default priority), so that graph capture works
+        self.stream = stream if stream is not None else torch.cuda.Stream()
+        reps = list(replicas)
+        arr = (ReplicaDesc * len(reps))(*[r.to_c() for r in reps])
+        self.replicas = reps
+        self.fmt = spin_format
+        self.cap = obs_capacity
+        h = C.c_void_p()
+        if torch_allocator:
+            self._alloc = _TorchAllocator(torch, torch.cuda.current_device(), self.stream)
+            _check(lib().islf_create_with_allocator(arr, len(reps), spin_format, obs_capacity,
+                                                    C.c_void_p(self.stream.cuda_stream), self._alloc.alloc,
+                                                    self._alloc.free, None, C.byref(h)))
+        else:
+            self._alloc = None
+            _check(lib().islf_create(arr, len(reps), spin_format, obs_capacity,
+                                     C.c_void_p(self.stream.cuda_stream), C.byref(h)))
+        self._h = h
+        self.set_exec(exec_mode)
+
+    # lifetime -------------------------------------------------------------
+    def close(self):
+        if getattr(self, "_h", None):
+            _check(lib().islf_destroy(self._h))
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    # spins ----------------------------------------------------------------
+    def _N(self, rep):
+        d = ReplicaDesc()
+        _check(lib().islf_get_desc(self._h, rep, C.byref(d)))
+        return d.Lx * d.Ly * d.Lz, (d.Lx, d.Ly, d.Lz)
+
+    def get_spins(self, rep=0) -> np.ndarray:
+        N, shape = self._N(rep)
+        out = np.empty(N, dtype=np.int8)
+        _check(lib().islf_get_spins(self._h, rep, out.ctypes.data_as(C.c_void_p), N))
+        return out
+
+    def set_spins(self, rep, spins):
+        s = np.ascontiguousarray(np.asarray(spins, dtype=np.int8).reshape(-1))
+        _check(lib().islf_set_spins(self._h, rep, s.ctypes.data_as(C.c_void_p), s.size))
+
+    # sweeps ---------------------------------------------------------------
+    def set_exec(self, mode: int):
+        _check(lib().islf_set_exec(self._h, mode))
+
+    def sweep(self, n: int = 1):
+        _check(lib().islf_sweep(self._h, n))
+
+    def sweep_count(self, rep=0) -> int:
+        t = C.c_uint64()
+        _check(lib().islf_sweep_count(self._h, rep, C.byref(t)))
+        return t.value
+
+    # measurement ----------------------------------------------------------
+    def measure(self, rep=0, first=0, count=None) -> np.ndarray:
+        if count is None:
+            count = self.sweep_count(rep) - first
+        out = np.zeros((count, 4), dtype=np.int64)
+        _check(lib().islf_measure(self._h, rep, first, count, out.ctypes.data_as(C.c_void_p)))
+        return out
+
+    def recompute(self, rep=0) -> np.ndarray:
+        o = Obs()
+        _check(lib().islf_recompute(self._h, rep, C.byref(o)))
+        return np.array([o.B, o.M, o.M1, o.Mn], dtype=np.int64)
+
+    def energy(self, rep=0, first=0, count=None) -> np.ndarray:
+        if count is None:
+            count = self.sweep_count(rep) - first
+        out = np.zeros(count, dtype=np.float64)
+        _check(lib().islf_energy(self._h, rep, first, count, out.ctypes.data_as(C.c_void_p)))
+        return out
+
+    def means(self, first, count) -> np.ndarray:
+        n = C.c_int32()
+        _check(lib().islf_num_replicas(self._h, C.byref(n)))
+        out = np.zeros((n.value, 5), dtype=np.float64)
+        _check(lib().islf_means(self._h, first, count, out.ctypes.data_as(C.c_void_p)))
+        return out
+
+    # batching / graphs / tuning -------------------------------------------
+    def add(self, replica: Replica) -> int:
+        slot = C.c_int32()
+        d = replica.to_c()
+        _check(lib().islf_batch_add(self._h, C.byref(d), C.byref(slot)))
+        return slot.value
+
+    def retire(self, slot: int):
+        _check(lib().islf_batch_retire(self._h, slot))
+
+    def capture(self, k_sweeps: int):
+        _check(lib().islf_graph_capture(self._h, k_sweeps))
+
+    def replay(self, n: int = 1):
+        _check(lib().islf_run_graph(self._h, n))
+
+    def get_tile(self, rep=0) -> int:
+        t = C.c_int32()
+        _check(lib().islf_get_tile(self._h, rep, C.byref(t)))
+        return t.value
+
+    def set_tile(self, rep, tile):
+        _check(lib().islf_set_tile(self._h, rep, tile))
+
+    def autotune(self, sweeps=4):
+        _check(lib().islf_autotune(self._h, sweeps))
+
+
+def num_tiles(spin_format=INT8) -> int:
+    n = C.c_int32()
+    _check(lib().islf_num_tiles(spin_format, C.byref(n)))
+    return n.value
+
+
+def footprint_bytes(replica: Replica, spin_format=INT8, obs_capacity=1024) -> int:
+    b = C.c_uint64()
+    d = replica.to_c()
+    _check(lib().islf_footprint_bytes(C.byref(d), spin_format, obs_capacity, C.byref(b)))
+    return b.value
+
+
+def integrate(h, m1, mn, c1=-1.0, cn=1.0, norm=1.0, stream=None):
+    """Cumulative trapezoid of g = norm (c1 m1 + cn mn) over h on the GPU (Eq. 9).
+
+    Inputs are torch float64 CUDA tensors (or array-likes, copied to the GPU).
+    Returns a float64 CUDA tensor.
+    """
+    torch = _torch()
+    dev = torch.device("cuda")
+    h = torch.as_tensor(h, dtype=torch.float64, device=dev).contiguous()
+    m1 = torch.as_tensor(m1, dtype=torch.float64, device=dev).contiguous()
+    mn = torch.as_tensor(mn, dtype=torch.float64, device=dev).contiguous()
+    out = torch.empty_like(h)
+    s = stream if stream is not None else torch.cuda.current_stream()
+    _check(lib().islf_integrate(C.c_void_p(h.data_ptr()), C.c_void_p(m1.data_ptr()), C.c_void_p(mn.data_ptr()),
+                                h.numel(), c1, cn, norm, C.c_void_p(out.data_ptr()), C.c_void_p(s.cuda_stream)))
+    return out

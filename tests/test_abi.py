@@ -1,0 +1,74 @@
+"""Host-side checks of the C ABI (no GPU needed).
+
+The library must load, export every entry point include/islf.h declares, and
+its host-only entry points (footprint, tile count, validation) must behave.
+"""
+import ctypes as C
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "islf.h")
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(islf_[a-z_]+)\s*\(", text)))
+
+
+@pytest.fixture(scope="module")
+def islf():
+    from paper_1411_5588_amd import islf as m
+    if not os.path.exists(m.LIB_PATH):
+        from paper_1411_5588_amd import build
+        build.build()
+    return m
+
+
+def test_header_declares_the_boundary():
+    names = declared_functions()
+    for required in ("islf_create", "islf_destroy", "islf_sweep", "islf_measure", "islf_integrate",
+                     "islf_set_spins", "islf_get_spins", "islf_energy", "islf_means", "islf_last_error"):
+        assert required in names
+
+
+def test_library_exports_every_declared_symbol(islf):
+    lib = C.CDLL(islf.LIB_PATH)
+    missing = [n for n in declared_functions() if not hasattr(lib, n)]
+    assert missing == []
+
+
+def test_footprint_and_validation(islf):
+    r = islf.Replica(160, 480, 600)
+    b8 = islf.footprint_bytes(r, islf.INT8, 2048)
+    bb = islf.footprint_bytes(r, islf.BITPACK, 2048)
+    assert b8 >= 160 * 480 * 600 and bb >= 160 * 480 * 600 // 8
+    assert bb < b8 / 4
+    for bad in (islf.Replica(0, 4, 4), islf.Replica(2, 1, 4), islf.Replica(2, 4, 5),
+                islf.Replica(2, 4, 4, ybc=7), islf.Replica(2, 4, 4, beta=-1.0),
+                islf.Replica(2, 4, 4, init=9), islf.Replica(2, 4, 4, h1=float("nan"))):
+        with pytest.raises(islf.IslfError) as e:
+            islf.footprint_bytes(bad)
+        assert e.value.status == islf.EINVAL
+    with pytest.raises(islf.IslfError) as e:
+        islf.footprint_bytes(islf.Replica(4096, 4096, 4096))
+    assert e.value.status == islf.ERANGE
+
+
+def test_tile_count(islf):
+    assert islf.num_tiles(islf.INT8) >= 8
+    assert islf.num_tiles(islf.BITPACK) >= 8
+    with pytest.raises(islf.IslfError):
+        islf.num_tiles(5)
+
+
+def test_product_package_never_imports_the_oracle():
+    pkg = os.path.join(ROOT, "paper_1411_5588_amd")
+    for dirpath, _, files in os.walk(pkg):
+        for f in files:
+            if f.endswith((".py", ".hip", ".cpp", ".h")):
+                text = open(os.path.join(dirpath, f)).read()
+                assert "oracle" not in text.lower(), f

@@ -1,0 +1,91 @@
+"""Batching, graphs and serving-style admission keep the arithmetic unchanged.
+
+A replica gives the same chain alone, in a batch of uneven shapes, admitted
+into a running batch at a later time, and under graph replay; retiring a
+neighbour does not disturb it.
+"""
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+if not torch.cuda.is_available():
+    pytest.skip("needs a GPU", allow_module_level=True)
+
+from oracle import oracle as O  # noqa: E402
+from paper_1411_5588_amd import islf  # noqa: E402
+
+from _helpers import config1, oracle_trajectory  # noqa: E402
+
+
+def batch_params():
+    return [config1(replica=0),
+            config1(Lx=20, Ly=64, Lz=64, beta=0.5, h1=0.25, hn=-0.25, replica=1),
+            config1(Lx=3, Ly=5, Lz=14, ybc=O.PBC, replica=2),
+            config1(Lx=40, Ly=32, Lz=40, beta=0.25, h1=0.75, hn=-0.75, replica=3)]
+
+
+@pytest.mark.parametrize("fmt", [islf.INT8, islf.BITPACK])
+@pytest.mark.parametrize("exec_mode", [islf.EXEC_BATCHED, islf.EXEC_PERSISTENT])
+def test_graph_replay_equals_stream_launches(fmt, exec_mode):
+    ps = batch_params()
+    with islf.Context([islf.Replica(**p) for p in ps], spin_format=fmt, obs_capacity=64,
+                      exec_mode=exec_mode) as ctx:
+        ctx.capture(4)
+        ctx.replay(5)
+        ctx.sweep(3)
+        ctx.replay(2)
+        recs = [ctx.measure(i, 0, 31) for i in range(len(ps))]
+        spins = [ctx.get_spins(i) for i in range(len(ps))]
+    for i, p in enumerate(ps):
+        _, o_rec, o_s = oracle_trajectory(p, 31)
+        assert np.array_equal(recs[i], o_rec), i
+        assert np.array_equal(spins[i], o_s), i
+
+
+def test_alone_equals_in_mix_with_admission_and_retirement():
+    ps = batch_params()
+    target = ps[1]
+    with islf.Context([islf.Replica(**ps[0]), islf.Replica(**ps[2])], obs_capacity=128) as ctx:
+        ctx.sweep(10)
+        slot = ctx.add(islf.Replica(**target))     # admitted while others are at sweep 10
+        ctx.sweep(5)
+        extra = ctx.add(islf.Replica(**ps[3]))
+        ctx.sweep(7)
+        ctx.retire(0)                              # a neighbour leaves
+        ctx.sweep(8)
+        got = ctx.measure(slot, 0, 20)
+        got_s = ctx.get_spins(slot)
+        t_extra = ctx.sweep_count(extra)
+        other = ctx.measure(1, 0, 30)
+    _, o_rec, o_s = oracle_trajectory(target, 20)
+    assert np.array_equal(got, o_rec)
+    assert np.array_equal(got_s, o_s)
+    assert t_extra == 15
+    _, o_rec2, _ = oracle_trajectory(ps[2], 30)
+    assert np.array_equal(other, o_rec2)
+
+
+def test_slot_reuse_after_retire():
+    ps = batch_params()
+    with islf.Context([islf.Replica(**ps[0]), islf.Replica(**ps[2])], obs_capacity=64) as ctx:
+        ctx.sweep(4)
+        ctx.retire(0)
+        s = ctx.add(islf.Replica(**ps[1]))
+        assert s == 0
+        ctx.sweep(6)
+        got = ctx.measure(0, 0, 6)
+        with pytest.raises(islf.IslfError):
+            ctx.measure(0, 0, 7)
+    _, o_rec, _ = oracle_trajectory(ps[1], 6)
+    assert np.array_equal(got, o_rec)
+
+
+def test_graph_invalidated_by_membership_change():
+    ps = batch_params()
+    with islf.Context([islf.Replica(**ps[0])], obs_capacity=16) as ctx:
+        ctx.capture(2)
+        ctx.add(islf.Replica(**ps[2]))
+        with pytest.raises(islf.IslfError) as e:
+            ctx.replay(1)
+        assert e.value.status == islf.ESTATE
