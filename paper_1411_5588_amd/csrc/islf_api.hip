@@ -66,12 +66,12 @@ static islf_status fail(islf_status st, const char *fmt, ...)
 extern "C" const char *islf_last_error(void) { return g_err.c_str(); }
 
 // ---------------------------------------------------------------------------
-// tile variants
-//  int8: a workgroup owns tj chunks x ty rows (tj*ty <= 256 threads) and each
-//        thread marches through mx x planes; tj is the most even split of the
-//        row's chunks into pieces of at most tj_max.
-//  bit-packed: 2^lj words x 2^ly rows x 2^(8-lj-ly) planes, one word each.
-//  seam phases (row y = 0, both formats): 2^lj_seam chunks/words x the rest in x.
+// tile variants (main phases, both formats): a workgroup owns tj columns x ty
+// rows (tj*ty <= 256 threads) and each thread marches through mx x planes;
+// a column is an 8-byte chunk (int8) or a 32-bit word of a sublattice row
+// (bit-packed), and tj is the most even split of a row's columns into pieces
+// of at most tj_max.  Seam phases (row y = 0): 2^lj_seam columns x the rest
+// of the 256 threads in x, one column each.
 // ---------------------------------------------------------------------------
 struct I8Tile {
     int tj_max, mx;
@@ -80,27 +80,23 @@ static const I8Tile kI8Tiles[] = {
     {16, 16}, {32, 16}, {64, 16}, {128, 16}, {256, 16}, {16, 8},  {32, 8},   {64, 8},
     {16, 32}, {32, 32}, {64, 32}, {128, 32}, {16, 64}, {32, 64}, {64, 64}, {256, 64},
 };
+static const I8Tile kBpTilesM[] = {
+    {16, 4}, {32, 4}, {64, 4}, {8, 4}, {4, 4}, {16, 2}, {16, 8}, {32, 8}, {8, 8}, {64, 8}, {4, 8}, {16, 16},
+};
+static const int kNumBpTilesM = (int)(sizeof(kBpTilesM) / sizeof(kBpTilesM[0]));
 static const int kNumI8Tiles = (int)(sizeof(kI8Tiles) / sizeof(kI8Tiles[0]));
 
-struct TileShape {
-    int lj, ly;
-};
-static const TileShape kBpTiles[] = {
-    {4, 4}, {5, 3}, {3, 5}, {6, 2}, {4, 2}, {3, 3}, {2, 4}, {5, 2}, {2, 6}, {1, 5}, {0, 6}, {1, 7},
-};
-static const int kNumBpTiles = (int)(sizeof(kBpTiles) / sizeof(kBpTiles[0]));
-
-static int num_tiles_of(int fmt) { return fmt == ISLF_SPIN_INT8 ? kNumI8Tiles : kNumBpTiles; }
+static int num_tiles_of(int fmt) { return fmt == ISLF_SPIN_INT8 ? kNumI8Tiles : kNumBpTilesM; }
 
 static long ceil_div(long a, long b) { return (a + b - 1) / b; }
 
 struct I8Shape {
     int tj, ty, mx;
 };
-static I8Shape i8_shape(const islf_replica_desc &d, int tile)
+static I8Shape i8_shape(const islf_replica_desc &d, int tile, int fmt = ISLF_SPIN_INT8)
 {
-    const long C = (d.Lz + 7) / 8;
-    const I8Tile &t = kI8Tiles[tile];
+    const long C = fmt == ISLF_SPIN_INT8 ? (d.Lz + 7) / 8 : (d.Lz + 63) / 64;
+    const I8Tile &t = fmt == ISLF_SPIN_INT8 ? kI8Tiles[tile] : kBpTilesM[tile];
     const long pieces = ceil_div(C, t.tj_max);
     I8Shape s;
     s.tj = (int)ceil_div(C, pieces);
@@ -113,16 +109,10 @@ static I8Shape i8_shape(const islf_replica_desc &d, int tile)
 static double tile_efficiency(const islf_replica_desc &d, int fmt, int tile)
 {
     const double ny = d.Ly - 1;
-    if (fmt == ISLF_SPIN_INT8) {
-        const long C = (d.Lz + 7) / 8;
-        const I8Shape s = i8_shape(d, tile);
-        const double entries = (double)ceil_div(d.Lx, s.mx) * ceil_div((long)ny, s.ty) * ceil_div(C, s.tj);
-        return (double)d.Lx * ny * C / (entries * kBlock * s.mx);
-    }
-    const long J = (d.Lz + 63) / 64;
-    const TileShape &s = kBpTiles[tile];
-    const long tj = 1l << s.lj, ty = 1l << s.ly, tx = 1l << (8 - s.lj - s.ly);
-    return (double)d.Lx * ny * J / ((double)ceil_div(d.Lx, tx) * tx * ceil_div((long)ny, ty) * ty * ceil_div(J, tj) * tj);
+    const long C = fmt == ISLF_SPIN_INT8 ? (d.Lz + 7) / 8 : (d.Lz + 63) / 64;
+    const I8Shape s = i8_shape(d, tile, fmt);
+    const double entries = (double)ceil_div(d.Lx, s.mx) * ceil_div((long)ny, s.ty) * ceil_div(C, s.tj);
+    return (double)d.Lx * ny * C / (entries * kBlock * s.mx);
 }
 
 static int default_tile(const islf_replica_desc *d, int fmt)
@@ -131,6 +121,7 @@ static int default_tile(const islf_replica_desc *d, int fmt)
     int best_i = 0;
     for (int i = 0; i < num_tiles_of(fmt); ++i) {
         if (fmt == ISLF_SPIN_INT8 && kI8Tiles[i].mx != 16) continue;
+        if (fmt == ISLF_SPIN_BITPACK && kBpTilesM[i].mx != 4) continue;
         const double eff = tile_efficiency(*d, fmt, i);
         if (eff > best + 1e-9) {
             best = eff;
@@ -301,26 +292,29 @@ static void build_work(Replica &R, int rep_id, int fmt)
         const I8Shape s = i8_shape(d, R.tile);
         for (int x0 = 0; x0 < d.Lx; x0 += s.mx)
             for (int y0 = 1; y0 < d.Ly; y0 += s.ty)
-                for (int j0 = 0; j0 < J; j0 += s.tj) R.main.push_back(Entry{rep_id, x0, y0, j0});
+                for (int j0 = 0; j0 < J; j0 += s.tj)
+                    R.main.push_back(Entry{rep_id, x0, y0, j0, std::min(s.mx, d.Lx - x0), 0, 0});
         R.d.i8_tj = s.tj;
         R.d.i8_ty = s.ty;
         R.d.i8_mx = s.mx;
         R.d.tile_lj = 0;
         R.d.tile_ly = 0;
     } else {
-        const TileShape &s = kBpTiles[R.tile];
-        const int tj = 1 << s.lj, ty = 1 << s.ly, tx = 1 << (8 - s.lj - s.ly);
-        for (int x0 = 0; x0 < d.Lx; x0 += tx)
-            for (int y0 = 1; y0 < d.Ly; y0 += ty)
-                for (int j0 = 0; j0 < J; j0 += tj) R.main.push_back(Entry{rep_id, x0, y0, j0});
-        R.d.tile_lj = s.lj;
-        R.d.tile_ly = s.ly;
-        R.d.i8_tj = R.d.i8_ty = R.d.i8_mx = 1;
+        const I8Shape s = i8_shape(d, R.tile, fmt);
+        for (int x0 = 0; x0 < d.Lx; x0 += s.mx)
+            for (int y0 = 1; y0 < d.Ly; y0 += s.ty)
+                for (int j0 = 0; j0 < J; j0 += s.tj)
+                    R.main.push_back(Entry{rep_id, x0, y0, j0, std::min(s.mx, d.Lx - x0), 0, 0});
+        R.d.i8_tj = s.tj;
+        R.d.i8_ty = s.ty;
+        R.d.i8_mx = s.mx;
+        R.d.tile_lj = 0;
+        R.d.tile_ly = 0;
     }
     const int lj = seam_lj(d, fmt);
     const int tjs = 1 << lj, txs = 1 << (8 - lj);
     for (int x0 = 0; x0 < d.Lx; x0 += txs)
-        for (int j0 = 0; j0 < J; j0 += tjs) R.seam.push_back(Entry{rep_id, x0, 0, j0});
+        for (int j0 = 0; j0 < J; j0 += tjs) R.seam.push_back(Entry{rep_id, x0, 0, j0, 1, 0, 0});
     R.d.tile_lj_seam = lj;
 }
 
@@ -399,6 +393,16 @@ static islf_status sync_tables(islf_ctx *c)
         c->seam_off[i] = (long)S.size();
         c->seam_len[i] = (long)R.seam.size();
         S.insert(S.end(), R.seam.begin(), R.seam.end());
+    }
+    long long slot = 0;
+    for (Entry &e : M) {
+        e.slot0 = slot;
+        slot += e.nsteps;
+    }
+    slot = 0;
+    for (Entry &e : S) {
+        e.slot0 = slot;
+        slot += e.nsteps;
     }
     if ((long)M.size() > c->main_cap) {
         dev_free(c, c->d_main);

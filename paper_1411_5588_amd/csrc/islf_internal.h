@@ -20,8 +20,13 @@ constexpr int kMaxMarch = 256;       // x planes one thread may march through pe
 // One tile of work for one replica: a box of rows/columns starting at
 // (x0, y0, j0) whose extent is the replica's tile shape.  j counts 8-byte
 // chunks (int8 format) or 32-bit words of one sublattice row (bit-packed).
+// A marching tile covers nsteps x planes from x0; the entries of one phase
+// list number their steps consecutively from slot0, so that a fixed grid can
+// split a list evenly at step granularity.
 struct Entry {
     int32_t rep, x0, y0, j0;
+    int32_t nsteps, pad_;
+    long long slot0;
 };
 
 // Read-only description of a replica as the kernels see it.

@@ -23,9 +23,10 @@
 
 namespace islf {
 
+// a ^ b ^ c in one gfx950 three-input bitwise op (truth table 0x96)
 __device__ __forceinline__ uint32_t xor3(uint32_t a, uint32_t b, uint32_t c)
 {
-    return a ^ b ^ c;
+    return __builtin_amdgcn_bitop3_b32(a, b, c, 0x96);
 }
 
 // ---------------------------------------------------------------------------
@@ -384,7 +385,8 @@ __device__ __forceinline__ StepIn load_step(const RepView &v, const MarchLane &L
 // moves the four sites of the phase to bytes 0, 2, 4, 6.  A flip adds its
 // packed (dB, dM) change to a register sum.
 template <bool NEVER, bool RAGGED>
-__device__ __forceinline__ void i8_march(const RepView &v, const Entry &en, int parity, const Tables *tb, Acc &a)
+__device__ __forceinline__ void i8_march(const RepView &v, const Entry &en, int k_lo, int k_hi, int parity,
+                                         const Tables *tb, Acc &a)
 {
     const int tid = threadIdx.x;
     const int ty = tid / v.tj;
@@ -394,8 +396,8 @@ __device__ __forceinline__ void i8_march(const RepView &v, const Entry &en, int 
     if (ty >= v.ty || y >= v.Ly || j >= v.C) return;
     const int Lx = v.Lx, Ly = v.Ly, C = v.C, Lz = v.Lz;
     const uint32_t Lzp = v.Lzp;
-    const int x0 = en.x0;
-    const int x1 = min(en.x0 + v.mx, Lx);
+    const int x0 = en.x0 + k_lo;
+    const int x1 = min(en.x0 + k_hi, Lx);
     const uint32_t xstride = (uint32_t)Ly * Lzp;
     const uint32_t jo = 8u * (uint32_t)j;
     const bool last = (j == C - 1);
@@ -483,21 +485,145 @@ __device__ __forceinline__ void i8_march(const RepView &v, const Entry &en, int 
     a.dMn += (dn - dBn) >> 16;
 }
 
+// Spreads the low 8 bits of x to bits 0, 4, 8, ..., 28 (one site per nibble).
+__device__ __forceinline__ uint32_t spread_nibbles(uint32_t x)
+{
+    x &= 0xFFu;
+    x = (x | (x << 12)) & 0x000F000Fu;
+    x = (x | (x << 6)) & 0x03030303u;
+    x = (x | (x << 3)) & 0x11111111u;
+    return x;
+}
+
+// bit-packed format, main phases (rows y >= 1): a thread owns word w of its
+// row's sublattices and marches through the x planes; at plane x it updates
+// the sublattice of the phase's parity (it alternates with x).  Neighbour
+// counts are bit-sliced; the 4-bit table index 8u + cnt of every site is
+// gathered into nibbles, eight sites per word.
+template <bool NEVER>
+__device__ __forceinline__ void bp_march(const RepView &v, const Entry &en, int k_lo, int k_hi, int parity,
+                                         const Tables *tb, Acc &a)
+{
+    const int tid = threadIdx.x;
+    const int ty = tid / v.tj;
+    const int tj = tid - ty * v.tj;
+    const int y = en.y0 + ty;
+    const int w = en.j0 + tj;
+    if (ty >= v.ty || y >= v.Ly || w >= v.Wq) return;
+    const int Lx = v.Lx, Ly = v.Ly, C = v.C, Wq = v.Wq;
+    const int nbits = v.Lz >> 1;
+    const uint32_t RW = 2u * (uint32_t)Wq;
+    const uint32_t xstride = (uint32_t)Ly * RW;
+    const uint32_t *words = (const uint32_t *)v.spins;
+    gu32 *wout = (gu32 *)v.spins;
+    const int nb_here = min(32, nbits - 32 * w);
+    const uint32_t vmask = nb_here >= 32 ? 0xFFFFFFFFu : ((1u << nb_here) - 1u);
+    const uint32_t seam_mask = v.seam_invert ? 0xFFFFFFFFu : 0u;
+    const int wl = (nbits - 1) >> 5, bl = (nbits - 1) & 31;   // last bit of a sublattice row
+    const int x0 = en.x0 + k_lo;
+    const int x1 = min(en.x0 + k_hi, Lx);
+    int dB = 0, dM = 0;
+    for (int x = x0; x < x1; ++x) {
+        const uint32_t row = (uint32_t)x * (uint32_t)Ly + (uint32_t)y;
+        const int q = (parity + x + y) & 1;
+        const uint32_t rb = row * RW;
+        const uint32_t own = rb + (uint32_t)(q * Wq + w);
+        const uint32_t othb = rb + (uint32_t)((q ^ 1) * Wq);
+        const uint32_t S = *(gcu32 *)(words + own);
+        const uint32_t O = *(gcu32 *)(words + othb + w);
+        uint32_t zm, zp;
+        if (q == 0) {
+            // z = 2i: z+1 is odd index i, z-1 is odd index i-1 (wrapping)
+            const uint32_t src = (w > 0) ? *(gcu32 *)(words + othb + w - 1) : *(gcu32 *)(words + othb + wl);
+            const uint32_t carry = (w > 0) ? (src >> 31) : ((src >> bl) & 1u);
+            zp = O;
+            zm = (O << 1) | carry;
+        } else {
+            // z = 2i+1: z-1 is even index i, z+1 is even index i+1 (wrapping)
+            const bool lastw = (w == Wq - 1);
+            const uint32_t inb = *(gcu32 *)(words + othb + (lastw ? 0 : w + 1)) & 1u;
+            zm = O;
+            zp = (O >> 1) | (inb << (lastw ? (nb_here - 1) : 31));
+        }
+        uint32_t yp;
+        if (y < Ly - 1) {
+            yp = *(gcu32 *)(words + own + RW);
+        } else {
+            const uint32_t xs = v.seam_reflect ? (uint32_t)(Lx - 1 - x) : (uint32_t)x;
+            yp = *(gcu32 *)(words + xs * (uint32_t)Ly * RW + (uint32_t)(q * Wq + w)) ^ seam_mask;
+        }
+        const uint32_t ym = *(gcu32 *)(words + own - RW);
+        const uint32_t xm = (x > 0) ? *(gcu32 *)(words + own - xstride) : 0u;
+        const uint32_t xp = (x < Lx - 1) ? *(gcu32 *)(words + own + xstride) : 0u;
+
+        const uint32_t s1 = zm ^ zp ^ ym, c1 = (zm & zp) | (ym & (zm ^ zp));
+        const uint32_t s2 = yp ^ xm ^ xp, c2 = (yp & xm) | (xp & (yp ^ xm));
+        const uint32_t b0 = s1 ^ s2, k0 = s1 & s2;
+        const uint32_t b1 = c1 ^ c2 ^ k0, b2 = (c1 & c2) | (k0 & (c1 ^ c2));
+
+        const int cls = (x == 0 ? 1 : 0) + (x == Lx - 1 ? 2 : 0);
+        const int k = 6 - (x == 0) - (x == Lx - 1);
+        const uint32_t gbase = row * (uint32_t)C + 8u * (uint32_t)w;
+        const TD *tdc = tb->td + cls * kThrPerClass;
+        const uint64_t *thc = tb->thr + cls * kThrPerClass;
+        uint32_t F = 0;
+#pragma unroll
+        for (int h = 0; h < 4; ++h) {
+            // eight sites 8h .. 8h+7: nibble i holds 8u + cnt of site 8h+i
+            const uint32_t nib = (spread_nibbles(S >> (8 * h)) << 3) | (spread_nibbles(b2 >> (8 * h)) << 2) |
+                                 (spread_nibbles(b1 >> (8 * h)) << 1) | spread_nibbles(b0 >> (8 * h));
+#pragma unroll
+            for (int g2 = 0; g2 < 2; ++g2) {
+                uint32_t rnd[4];
+                philox10(((gbase + (uint32_t)(2 * h + g2)) << 1) | (uint32_t)q, v.t, v.replica, 0u, v.key0,
+                         v.key1, rnd);
+#pragma unroll
+                for (int l = 0; l < 4; ++l) {
+                    const int i = 4 * g2 + l;
+                    const uint32_t e = (nib >> (4 * i)) & 0xFu;
+                    bool acc;
+                    if (NEVER) acc = (uint64_t)rnd[l] < thc[e];
+                    else acc = rnd[l] <= tdc[e].thr_m1;
+                    F |= (uint32_t)acc << (8 * h + i);
+                }
+            }
+        }
+        F &= vmask;
+        wout[own] = S ^ F;
+        const uint32_t FU = F & S;
+        const int nf = __popc(F), nfu = __popc(FU);
+        const int Sf = __popc(F & b0) + 2 * __popc(F & b1) + 4 * __popc(F & b2);
+        const int Sfu = __popc(FU & b0) + 2 * __popc(FU & b1) + 4 * __popc(FU & b2);
+        const int db = -2 * (4 * Sfu - 2 * k * nfu - 2 * Sf + k * nf);
+        const int dm = 2 * nf - 4 * nfu;
+        dB += db;
+        dM += dm;
+        if (x == 0) a.dM1 += dm;
+        if (x == Lx - 1) a.dMn += dm;
+    }
+    a.dB += dB;
+    a.dM += dM;
+}
+
 // ---------------------------------------------------------------------------
 // Processing of a contiguous range of work entries by one workgroup.
 // ---------------------------------------------------------------------------
 template <int FMT, bool SEAM>
-__device__ __forceinline__ void process_range(const RepDesc *__restrict__ descs,
-                                              const RepState *__restrict__ st,
-                                              const Entry *__restrict__ work, long e0, long e1, int parity,
-                                              uint32_t t_offset, Tables *tb)
+__device__ __forceinline__ void process_slots(const RepDesc *__restrict__ descs, const RepState *__restrict__ st,
+                                              const Entry *__restrict__ work, long n_entries, long e_begin,
+                                              long long s0, long long s1, int parity, uint32_t t_offset,
+                                              Tables *tb)
 {
     const bool seam = SEAM;
     Acc a = {0, 0, 0, 0};
     int cur_rep = -1;
     RepView v;
-    for (long e = e0; e < e1; ++e) {
+    for (long e = e_begin; e < n_entries; ++e) {
         const Entry en = work[e];
+        if (en.slot0 >= s1) break;
+        const int k_lo = (int)max(0ll, s0 - en.slot0);
+        const int k_hi = (int)min((long long)en.nsteps, s1 - en.slot0);
+        if (k_lo >= k_hi) continue;
         if (en.rep != cur_rep) {
             if (cur_rep >= 0) flush_acc(a, v.acc, v.t, blockIdx.x & (kAccSlots - 1));
             cur_rep = en.rep;
@@ -508,12 +634,17 @@ __device__ __forceinline__ void process_range(const RepDesc *__restrict__ descs,
         if (FMT == ISLF_SPIN_INT8 && !seam) {
             const bool ragged = (v.Lz & 7) != 0;
             if (v.never) {
-                if (ragged) i8_march<true, true>(v, en, parity, tb, a);
-                else i8_march<true, false>(v, en, parity, tb, a);
+                if (ragged) i8_march<true, true>(v, en, k_lo, k_hi, parity, tb, a);
+                else i8_march<true, false>(v, en, k_lo, k_hi, parity, tb, a);
             } else {
-                if (ragged) i8_march<false, true>(v, en, parity, tb, a);
-                else i8_march<false, false>(v, en, parity, tb, a);
+                if (ragged) i8_march<false, true>(v, en, k_lo, k_hi, parity, tb, a);
+                else i8_march<false, false>(v, en, k_lo, k_hi, parity, tb, a);
             }
+            continue;
+        }
+        if (FMT == ISLF_SPIN_BITPACK && !seam) {
+            if (v.never) bp_march<true>(v, en, k_lo, k_hi, parity, tb, a);
+            else bp_march<false>(v, en, k_lo, k_hi, parity, tb, a);
             continue;
         }
         const int tid = threadIdx.x;
@@ -530,8 +661,21 @@ __device__ __forceinline__ void process_range(const RepDesc *__restrict__ descs,
     if (cur_rep >= 0) flush_acc(a, v.acc, v.t, blockIdx.x & (kAccSlots - 1));
 }
 
-// One phase of one sweep over the entries [0, n_entries): block b takes the
-// contiguous range [b*n/G, (b+1)*n/G).
+// First entry of a phase list whose steps reach past slot s (binary search).
+__device__ __forceinline__ long find_entry(const Entry *__restrict__ work, long n, long long s)
+{
+    long lo = 0, hi = n;
+    while (lo < hi) {
+        const long mid = (lo + hi) >> 1;
+        const Entry en = work[mid];
+        if (en.slot0 + en.nsteps <= s) lo = mid + 1;
+        else hi = mid;
+    }
+    return lo;
+}
+
+// One phase of one sweep: workgroup b takes entry b whole (the hardware
+// dispatcher balances the load over the chip).
 template <int FMT, bool SEAM>
 __global__ __launch_bounds__(kBlock) void k_phase(const RepDesc *__restrict__ descs,
                                                   const RepState *__restrict__ st,
@@ -539,10 +683,9 @@ __global__ __launch_bounds__(kBlock) void k_phase(const RepDesc *__restrict__ de
                                                   int phase)
 {
     __shared__ Tables tb;
-    const long G = gridDim.x;
-    const long e0 = (long)blockIdx.x * n_entries / G;
-    const long e1 = (long)(blockIdx.x + 1) * n_entries / G;
-    process_range<FMT, SEAM>(descs, st, work, e0, e1, phase & 1, 0u, &tb);
+    const long b = blockIdx.x;
+    const Entry en = work[b];
+    process_slots<FMT, SEAM>(descs, st, work, b + 1, b, en.slot0, en.slot0 + en.nsteps, phase & 1, 0u, &tb);
 }
 
 // End of a sweep: fold the spread partial sums into the running observables,
@@ -630,8 +773,17 @@ __global__ __launch_bounds__(kBlock) void k_persistent(const RepDesc *__restrict
     unsigned long long passed = 0;
     for (uint32_t s = 0; s < n_sweeps; ++s) {
         for (int p = 0; p < 4; ++p) {
-            if (p >= 2) process_range<FMT, true>(descs, st, work_seam, b * n_seam / G, (b + 1) * n_seam / G, p & 1, s, &tb);
-            else process_range<FMT, false>(descs, st, work_main, b * n_main / G, (b + 1) * n_main / G, p & 1, s, &tb);
+            // an even split of the phase's x steps over the fixed grid
+            const Entry *work = p >= 2 ? work_seam : work_main;
+            const long n = p >= 2 ? n_seam : n_main;
+            if (n > 0) {
+                const Entry tail = work[n - 1];
+                const long long S = tail.slot0 + tail.nsteps;
+                const long long s0 = b * S / G, s1 = (b + 1) * S / G;
+                const long eb = find_entry(work, n, s0);
+                if (p >= 2) process_slots<FMT, true>(descs, st, work, n, eb, s0, s1, p & 1, s, &tb);
+                else process_slots<FMT, false>(descs, st, work, n, eb, s0, s1, p & 1, s, &tb);
+            }
             if (!grid_barrier(sync, (unsigned long long)G, passed)) return;
         }
         // bookkeeping of sweep s: replica i is folded by block i mod G while
@@ -898,14 +1050,15 @@ hipError_t launch_phase(int fmt, const RepDesc *descs, const RepState *st, const
                         int phase, int grid, hipStream_t s)
 {
     if (n <= 0) return hipSuccess;
-    if (grid > n) grid = (int)n;
+    (void)grid;
+    const unsigned int blocks = (unsigned int)n;   // one entry per workgroup
     const bool seam = phase >= 2;
     if (fmt == ISLF_SPIN_INT8) {
-        if (seam) hipLaunchKernelGGL((k_phase<ISLF_SPIN_INT8, true>), dim3(grid), dim3(kBlock), 0, s, descs, st, work, n, phase);
-        else hipLaunchKernelGGL((k_phase<ISLF_SPIN_INT8, false>), dim3(grid), dim3(kBlock), 0, s, descs, st, work, n, phase);
+        if (seam) hipLaunchKernelGGL((k_phase<ISLF_SPIN_INT8, true>), dim3(blocks), dim3(kBlock), 0, s, descs, st, work, n, phase);
+        else hipLaunchKernelGGL((k_phase<ISLF_SPIN_INT8, false>), dim3(blocks), dim3(kBlock), 0, s, descs, st, work, n, phase);
     } else {
-        if (seam) hipLaunchKernelGGL((k_phase<ISLF_SPIN_BITPACK, true>), dim3(grid), dim3(kBlock), 0, s, descs, st, work, n, phase);
-        else hipLaunchKernelGGL((k_phase<ISLF_SPIN_BITPACK, false>), dim3(grid), dim3(kBlock), 0, s, descs, st, work, n, phase);
+        if (seam) hipLaunchKernelGGL((k_phase<ISLF_SPIN_BITPACK, true>), dim3(blocks), dim3(kBlock), 0, s, descs, st, work, n, phase);
+        else hipLaunchKernelGGL((k_phase<ISLF_SPIN_BITPACK, false>), dim3(blocks), dim3(kBlock), 0, s, descs, st, work, n, phase);
     }
     return hipGetLastError();
 }
