@@ -1,23 +1,27 @@
 """Throughput benchmark: spin updates/ns of checkerboard Metropolis sweeps.
 
-Workload (default): the paper-scale thin film 160 x 480 x 600 (46.08 M sites),
+Workload: the paper-scale thin film 160 x 480 x 600 (46.08 M sites),
 generalized antiperiodic y boundary, J = 1, h1 = +0.55 on x = 0 and
 hn = -0.55 on x = Lx-1, random initial state from the seed, one replica per
-temperature T in {2, 3, 4} (beta = 1/T), all three swept together in one
-persistent, graph-captured launch.  A step is one sweep of every replica:
-four checkerboard phases with the fused per-sweep observable reductions.
-Inputs are synthetic (seeded), resident in HBM before timing starts.
+temperature T in {2, 3, 4} (beta = 1/T), all three swept together by one
+graph launch per chunk of sweeps.  A step is one sweep of every replica: four
+checkerboard phases with the fused per-sweep observable reductions and the
+per-sweep record.  Inputs are synthetic (seeded) and resident in HBM before
+timing starts; nothing is copied to the host inside the timed region.
 
-Prints one JSON line (rank 0, one GPU).  Also reports the plain
-one-lattice-per-launch form and the bit-packed spin format on the same
-workload, the roofline of the dominant kernel, and the CPU oracle timed on a
-bounded sample of the same workload.
+Prints one JSON line.  Besides the headline (bit-packed spins, batched form)
+it reports the int8 format and the plain one-lattice-per-launch and
+persistent forms on the same workload, the roofline of the dominant kernel
+(the main-phase update kernel, timed live with HIP events on the context's
+stream) and the CPU oracle timed on a bounded sample of the same workload.
 """
 from __future__ import annotations
 
 import argparse
+import hashlib
 import json
 import os
+import re
 import sys
 import time
 
@@ -30,11 +34,18 @@ TEMPS = (2.0, 3.0, 4.0)
 H1 = 0.55
 SEED = 14115588
 
-# MI355X published peaks and unit counts
+# MI355X: 256 CUs x 4 SIMDs x 16 lanes at 2.4 GHz issue 39.3 T 32-bit VALU
+# lane-operations per second; HBM3E peak 8 TB/s.
+VALU_PEAK_TOPS = 256 * 4 * 16 * 2.4e9 / 1e12
 HBM_PEAK_GBS = 8000.0
-NUM_CU = 256
-CLOCK_GHZ = 2.4
-LANES_PER_CU = 64          # VALU lanes per CU per clock (4 SIMDs x 16)
+# algorithmic integer operations per spin update: Philox4x32-10 gives four
+# words for 10 rounds x (2 multiply-hi/lo + 2 three-input xor) = 40 operations,
+# i.e. 10 per update; the Metropolis test adds 7 (5 adds for the six-neighbour
+# sum, 1 compare against the tabulated threshold, 1 select of the flip).
+OPS_PER_UPDATE = 17
+BYTES_PER_UPDATE = {"int8": 2.0, "bitpack": 0.25}   # each spin read and written once per sweep
+PROFILE_TRAFFIC = os.path.join(ROOT, "profiles", "traffic_main_phase_160x480x600x3.md")
+KERNEL_SOURCE = os.path.join(ROOT, "paper_1411_5588_amd", "csrc", "islf_kernels.hip")
 
 
 def parse():
@@ -44,10 +55,12 @@ def parse():
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--chunk", type=int, default=50, help="sweeps per captured graph launch")
     ap.add_argument("--form", choices=["persistent", "batched", "plain"], default="batched")
-    ap.add_argument("--fmt", choices=["int8", "bitpack"], default="int8")
-    ap.add_argument("--no-extras", action="store_true", help="skip the plain / bit-packed side runs")
+    ap.add_argument("--fmt", choices=["int8", "bitpack"], default="bitpack")
+    ap.add_argument("--no-extras", action="store_true", help="skip the other forms and formats")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--cpu-sweeps", type=int, default=3)
+    ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
+                    help="only run a plain device copy of MIB MiB (traffic counter calibration)")
     return ap.parse_args()
 
 
@@ -57,12 +70,11 @@ def replicas(islf):
                          replica=i, init=islf.INIT_RANDOM) for i, T in enumerate(TEMPS)]
 
 
-def run_form(islf, torch, form, fmt, steps, warmup, chunk):
-    """Returns (ms per sweep, kernel ms per launch, launches, sweeps per launch)."""
+def run_form(islf, torch, form, fmt, steps, warmup, chunk, timings=False):
     mode = {"persistent": islf.EXEC_PERSISTENT, "batched": islf.EXEC_BATCHED, "plain": islf.EXEC_PLAIN}[form]
     f = {"int8": islf.INT8, "bitpack": islf.BITPACK}[fmt]
     reps = replicas(islf)
-    ctx = islf.Context(reps, spin_format=f, obs_capacity=steps + warmup + 8, exec_mode=mode)
+    ctx = islf.Context(reps, spin_format=f, obs_capacity=steps + warmup + 64, exec_mode=mode)
     try:
         chunk = max(1, min(chunk, steps))
         if warmup:
@@ -70,35 +82,47 @@ def run_form(islf, torch, form, fmt, steps, warmup, chunk):
         ctx.capture(chunk)
         n_launch = steps // chunk
         rest = steps - n_launch * chunk
-        torch.cuda.synchronize()
         s = ctx.stream
-        starts = [torch.cuda.Event(enable_timing=True) for _ in range(n_launch)]
-        ends = [torch.cuda.Event(enable_timing=True) for _ in range(n_launch)]
         t0 = torch.cuda.Event(enable_timing=True)
         t1 = torch.cuda.Event(enable_timing=True)
         torch.cuda.synchronize()
-        wall0 = time.perf_counter()
         t0.record(s)
-        for i in range(n_launch):
-            starts[i].record(s)
+        for _ in range(n_launch):
             ctx.replay(1)
-            ends[i].record(s)
         if rest:
             ctx.sweep(rest)
         t1.record(s)
         torch.cuda.synchronize()
-        wall = time.perf_counter() - wall0
         total_ms = t0.elapsed_time(t1)
-        per_launch = [a.elapsed_time(b) for a, b in zip(starts, ends)]
-        # the run must be whole: every replica advanced by warmup + steps sweeps
         for i in range(len(reps)):
             assert ctx.sweep_count(i) == warmup + steps
-        rec = ctx.measure(0, warmup + steps - 1, 1)
-        assert rec.shape == (1, 4)
-        return dict(ms_per_sweep=total_ms / steps, wall_s=wall, launch_ms=sum(per_launch) / max(1, len(per_launch)),
-                    sweeps_per_launch=chunk, launches=n_launch)
+        out = dict(ms_per_sweep=total_ms / steps, sweeps_per_launch=chunk, launches=n_launch)
+        if timings:
+            ms, cnt = ctx.phase_timings(8)
+            out["kernel_ms"] = {"main_phase": float(ms[0]), "seam_phase": float(ms[1]), "end_of_sweep": float(ms[2])}
+            out["kernel_launches"] = [int(c) for c in cnt]
+        return out
     finally:
         ctx.close()
+
+
+def kernel_source_hash():
+    with open(KERNEL_SOURCE, "rb") as f:
+        return hashlib.sha256(f.read()).hexdigest()[:16]
+
+
+def committed_traffic(fmt):
+    """HBM bytes per main-phase dispatch from the committed counter summary,
+    or None when the kernel source has changed since it was taken."""
+    try:
+        text = open(PROFILE_TRAFFIC).read()
+    except OSError:
+        return None
+    m = re.search(r"kernel_source_sha256_16:\s*([0-9a-f]+)", text)
+    if not m or m.group(1) != kernel_source_hash():
+        return None
+    m = re.search(rf"traffic_bytes_per_dispatch\[{fmt}\]:\s*([0-9.eE+]+)", text)
+    return float(m.group(1)) if m else None
 
 
 def cpu_baseline(n_sweeps):
@@ -110,16 +134,16 @@ def cpu_baseline(n_sweeps):
     L.run(n_sweeps)
     dt = time.perf_counter() - t
     N = Lx * Ly * Lz
-    return dict(value=N * n_sweeps / (dt * 1e9), unit="spin updates/ns", cores=1, kind="oracle",
-                sample=f"{n_sweeps} sweeps of one {Lx}x{Ly}x{Lz} replica (T=3), observables recomputed "
-                       f"after each sweep, {dt:.1f} s on the host CPU")
+    return dict(value=round(N * n_sweeps / (dt * 1e9), 5), unit="spin updates/ns", cores=1, kind="oracle",
+                sample=f"{n_sweeps} sweeps of one {Lx}x{Ly}x{Lz} replica (T=3, GAPBC, h1=+-{H1}), observables "
+                       f"recomputed after each sweep; {dt:.1f} s single-threaded on the host CPU")
 
 
 def main():
     args = parse()
     if args.gpus != 1:
-        print(f"bench.py measures one GPU only (asked for --gpus {args.gpus}); the sweep path is "
-              f"single-GPU and multi-GPU sharding is not part of this build", file=sys.stderr)
+        print(f"bench.py measures one GPU only (asked for --gpus {args.gpus}): the sweep path runs on a "
+              f"single GPU and sharding across GPUs is not part of this build", file=sys.stderr)
         sys.exit(2)
     import torch
 
@@ -127,48 +151,60 @@ def main():
     if not torch.cuda.is_available():
         print("no GPU available", file=sys.stderr)
         sys.exit(1)
+    if args.calibrate_copy:
+        n = args.calibrate_copy << 20
+        a = torch.empty(n, dtype=torch.uint8, device="cuda")
+        b = torch.empty_like(a)
+        a.fill_(1)
+        torch.cuda.synchronize()
+        b.copy_(a)
+        torch.cuda.synchronize()
+        print(json.dumps({"calibration_copy_bytes": n}), flush=True)
+        return
+
     Lx, Ly, Lz = SHAPE
     N = Lx * Ly * Lz
     n_reps = len(TEMPS)
     updates_per_sweep = N * n_reps
 
-    main_run = run_form(islf, torch, args.form, args.fmt, args.steps, args.warmup, args.chunk)
+    main_run = run_form(islf, torch, args.form, args.fmt, args.steps, args.warmup, args.chunk, timings=True)
     print(f"# {args.form}/{args.fmt}: {main_run}", file=sys.stderr, flush=True)
     value = updates_per_sweep / (main_run["ms_per_sweep"] * 1e6)
 
-    extras = {}
+    forms = {}
     if not args.no_extras:
-        for form, fmt in (("plain", "int8"), ("batched", "bitpack")):
+        for form, fmt in (("plain", "bitpack"), ("batched", "int8"), ("plain", "int8"), ("persistent", "bitpack")):
             if (form, fmt) == (args.form, args.fmt):
                 continue
             r = run_form(islf, torch, form, fmt, min(args.steps, 100), 5, min(args.chunk, 50))
-            extras[f"{form}_{fmt}"] = round(updates_per_sweep / (r["ms_per_sweep"] * 1e6), 2)
+            forms[f"{form}_{fmt}"] = round(updates_per_sweep / (r["ms_per_sweep"] * 1e6), 2)
             print(f"# {form}/{fmt}: {r}", file=sys.stderr, flush=True)
 
-    # roofline of the dominant kernel (the sweep kernel: one launch covers
-    # sweeps_per_launch sweeps of all replicas)
-    bytes_per_update = 2.0 if args.fmt == "int8" else 0.25
-    sweeps_per_launch = main_run["sweeps_per_launch"]
-    launch_s = main_run["launch_ms"] * 1e-3
-    achieved_gbs = bytes_per_update * updates_per_sweep * sweeps_per_launch / launch_s / 1e9
-    roofline = {"bound": "hbm", "achieved": round(achieved_gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": round(achieved_gbs / HBM_PEAK_GBS, 4), "traffic": None}
+    # dominant kernel: the main-phase update kernel; one launch updates the
+    # sites of one main phase (rows y >= 1, one parity) of all replicas
+    main_ms = main_run["kernel_ms"]["main_phase"]
+    updates_per_launch = n_reps * Lx * (Ly - 1) * Lz / 2
+    achieved_tops = OPS_PER_UPDATE * updates_per_launch / (main_ms * 1e-3) / 1e12
+    traffic = committed_traffic(args.fmt)
+    roofline = {"bound": "alu", "achieved": round(achieved_tops, 2), "peak": round(VALU_PEAK_TOPS, 1),
+                "unit": "T int-op/s", "frac": round(achieved_tops / VALU_PEAK_TOPS, 4), "traffic": traffic,
+                "kernel": "main-phase update", "kernel_ms": round(main_ms, 5),
+                "ops_per_update": OPS_PER_UPDATE,
+                "hbm_view": {"algorithmic_GBs": round(BYTES_PER_UPDATE[args.fmt] * updates_per_launch
+                                                      / (main_ms * 1e-3) / 1e9, 1),
+                             "peak_GBs": HBM_PEAK_GBS}}
 
-    cpu = None
-    if not args.no_cpu:
-        cpu = cpu_baseline(args.cpu_sweeps)
-        cpu["value"] = round(cpu["value"], 5)
-
+    cpu = None if args.no_cpu else cpu_baseline(args.cpu_sweeps)
     line = {
         "metric": "spin updates/ns", "value": round(value, 2), "unit": "spin updates/ns", "n_gpus": 1,
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(main_run["ms_per_sweep"], 5),
-        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": args.fmt if args.fmt == "int8" else "u32",
-        "data": "synthetic",
-        "config": {"workload": f"thin film {Lx}x{Ly}x{Lz} GAPBC, h1=+{H1}/hn=-{H1}, T in {list(TEMPS)}, "
-                               f"{n_reps} replicas in one {args.form} graph-captured launch, {args.fmt} spins",
-                   "sites_per_replica": N, "replicas": n_reps, "form": args.form, "spin_format": args.fmt,
-                   "sweeps_per_launch": sweeps_per_launch},
-        "forms": extras,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "u32" if args.fmt == "bitpack" else "int8", "data": "synthetic",
+        "config": {"workload": f"thin film {Lx}x{Ly}x{Lz} GAPBC, h1=+{H1}/hn=-{H1}, one replica per T in "
+                               f"{list(TEMPS)}, {args.fmt} spins, {args.form} form, "
+                               f"{main_run['sweeps_per_launch']} sweeps per graph launch",
+                   "sites_per_replica": N, "replicas": n_reps, "form": args.form, "spin_format": args.fmt},
+        "forms": forms,
         "roofline": roofline,
         "cpu_baseline": cpu,
     }

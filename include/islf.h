@@ -225,6 +225,14 @@ islf_status islf_get_tile(const islf_ctx *ctx, int32_t rep, int32_t *tile);
 islf_status islf_set_tile(islf_ctx *ctx, int32_t rep, int32_t tile);
 islf_status islf_autotune(islf_ctx *ctx, uint32_t sweeps);
 
+/* Runs n_sweeps sweeps of every live replica one kernel at a time (batched
+ * form, no graph) with HIP events around each launch on the context's stream,
+ * and returns the mean duration in milliseconds and the launch count of each
+ * kernel kind: [0] main phases (rows y >= 1), [1] seam phases (row y = 0),
+ * [2] end-of-sweep bookkeeping.  The sweeps are real (they advance the
+ * chains).  Synchronises.  Errors: EINVAL, EDEVICE, ERANGE. */
+islf_status islf_phase_timings(islf_ctx *ctx, uint32_t n_sweeps, double *mean_ms, uint32_t *launches);
+
 /* Thread-local message describing the last failure on this thread. */
 const char *islf_last_error(void);
 

@@ -553,7 +553,7 @@ extern "C" islf_status islf_create_with_allocator(const islf_replica_desc *reps,
     if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, persistent_kernel(spin_format), kBlock, 0) != hipSuccess ||
         per_cu < 1)
         per_cu = 1;
-    c->persistent_grid = c->num_cu * std::min(per_cu, 8);
+    c->persistent_grid = std::min(c->num_cu * std::min(per_cu, 8), kBarrierGroup * kMaxGroups);
     c->d_sync = (GridSync *)dev_alloc(c, sizeof(GridSync));
     c->d_scratch = (unsigned long long *)dev_alloc(c, 64 * sizeof(unsigned long long));
     if (!c->d_sync || !c->d_scratch) {
@@ -724,10 +724,15 @@ extern "C" islf_status islf_sweep(islf_ctx *ctx, uint32_t n_sweeps)
 
 static islf_status check_device_error(islf_ctx *c)
 {
-    GridSync h;
-    HIP_TRY(hipMemcpyAsync(&h, c->d_sync, sizeof(unsigned int) * 4, hipMemcpyDeviceToHost, c->stream));
+    unsigned long long err = 0;
+    HIP_TRY(hipMemcpyAsync(&err, &c->d_sync->error.v, sizeof err, hipMemcpyDeviceToHost, c->stream));
     HIP_TRY(hipStreamSynchronize(c->stream));
-    if (h.error) return fail(ISLF_EDEVICE, "a persistent-kernel barrier timed out");
+    if (err) {
+        // clear it so that the context stays usable
+        HIP_TRY(launch_zero((unsigned long long *)&c->d_sync->error, 16, c->stream));
+        HIP_TRY(hipStreamSynchronize(c->stream));
+        return fail(ISLF_EDEVICE, "a persistent-kernel barrier timed out");
+    }
     return ISLF_OK;
 }
 
@@ -977,4 +982,61 @@ extern "C" islf_status islf_autotune(islf_ctx *ctx, uint32_t sweeps)
     (void)ctx;
     (void)sweeps;
     return fail(ISLF_ESTATE, "autotune not available yet");
+}
+
+extern "C" islf_status islf_phase_timings(islf_ctx *ctx, uint32_t n_sweeps, double *mean_ms, uint32_t *launches)
+{
+    if (!ctx || !mean_ms || !launches) return fail(ISLF_EINVAL, "NULL argument");
+    if (n_sweeps < 1) return fail(ISLF_EINVAL, "n_sweeps must be >= 1");
+    islf_status st = sync_tables(ctx);
+    if (st != ISLF_OK) return st;
+    st = check_sweep_range(ctx, n_sweeps);
+    if (st != ISLF_OK) return st;
+    const int nl = (int)ctx->live.size();
+    const int per_sweep = 5;
+    std::vector<hipEvent_t> ev(2 * per_sweep * (size_t)n_sweeps, nullptr);
+    for (auto &e : ev)
+        if (hipEventCreate(&e) != hipSuccess) {
+            for (auto &f : ev)
+                if (f) (void)hipEventDestroy(f);
+            return fail(ISLF_EDEVICE, "cannot create events");
+        }
+    hipError_t err = hipSuccess;
+    for (uint32_t s = 0; s < n_sweeps && err == hipSuccess; ++s) {
+        for (int p = 0; p < 4 && err == hipSuccess; ++p) {
+            const bool seam = p >= 2;
+            hipEvent_t *e = &ev[2 * (per_sweep * (size_t)s + p)];
+            err = hipEventRecord(e[0], ctx->stream);
+            if (err == hipSuccess)
+                err = launch_phase(ctx->fmt, ctx->d_desc, ctx->d_state, seam ? ctx->d_seam : ctx->d_main,
+                                   seam ? ctx->n_seam : ctx->n_main, p, ctx->max_grid, ctx->stream);
+            if (err == hipSuccess) err = hipEventRecord(e[1], ctx->stream);
+        }
+        hipEvent_t *e = &ev[2 * (per_sweep * (size_t)s + 4)];
+        if (err == hipSuccess) err = hipEventRecord(e[0], ctx->stream);
+        if (err == hipSuccess) err = launch_end_sweep(ctx->d_desc, ctx->d_state, ctx->d_live, nl, ctx->stream);
+        if (err == hipSuccess) err = hipEventRecord(e[1], ctx->stream);
+    }
+    if (err == hipSuccess) err = hipStreamSynchronize(ctx->stream);
+    double sum[3] = {0, 0, 0};
+    uint32_t cnt[3] = {0, 0, 0};
+    if (err == hipSuccess) {
+        for (uint32_t s = 0; s < n_sweeps; ++s)
+            for (int k = 0; k < per_sweep; ++k) {
+                float ms = 0.f;
+                hipEvent_t *e = &ev[2 * (per_sweep * (size_t)s + k)];
+                if (hipEventElapsedTime(&ms, e[0], e[1]) != hipSuccess) continue;
+                const int kind = k < 2 ? 0 : (k < 4 ? 1 : 2);
+                sum[kind] += ms;
+                cnt[kind] += 1;
+            }
+    }
+    for (auto &e : ev) (void)hipEventDestroy(e);
+    if (err != hipSuccess) return fail(ISLF_EDEVICE, "timed sweeps failed: %s", hipGetErrorString(err));
+    for (int r : ctx->live) ctx->reps[r].t_host += n_sweeps;
+    for (int k = 0; k < 3; ++k) {
+        mean_ms[k] = cnt[k] ? sum[k] / cnt[k] : 0.0;
+        launches[k] = cnt[k];
+    }
+    return ISLF_OK;
 }

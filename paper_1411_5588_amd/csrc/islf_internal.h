@@ -63,12 +63,23 @@ struct RepState {
 };
 
 // Persistent-kernel synchronisation words (device memory, zero-initialised).
-// The arrival counter only ever changes through read-modify-write atomics
-// (it is re-zeroed by a fill kernel before each persistent launch).
+// Two-level grid barrier state.  Blocks arrive at their group's counter; the
+// last arrival of a group arrives at the top counter, waits for all groups,
+// then bumps its group's release counter, which the group's other blocks
+// poll.  Every counter only changes through read-modify-write atomics and is
+// re-zeroed by a fill kernel before each persistent launch; each sits on its
+// own 128-byte line.
+constexpr int kBarrierGroup = 32;     // blocks per group
+constexpr int kMaxGroups = 128;       // up to 4096 blocks
+struct SyncLine {
+    unsigned long long v;
+    unsigned long long pad_[15];
+};
 struct GridSync {
-    unsigned long long count;
-    unsigned int error;
-    unsigned int pad_[61];
+    SyncLine top;
+    SyncLine error;
+    SyncLine arrive[kMaxGroups];
+    SyncLine release[kMaxGroups];
 };
 
 }  // namespace islf

@@ -729,30 +729,47 @@ __global__ void k_end_sweep(const RepDesc *__restrict__ descs, RepState *__restr
 // Persistent form: all sweeps of all replicas in one launch; phases are
 // separated by a grid-wide barrier with a bounded wait.
 // ---------------------------------------------------------------------------
-// Barrier number k of a launch completes when the monotonic arrival counter
-// reaches (k+1) * nblocks.  Only atomic read-modify-writes touch the counter
-// (the host re-zeroes it with a fill kernel before each launch), and the
-// wait is bounded: on time-out the error word is set and the kernel ends.
+__device__ __forceinline__ unsigned long long sync_load(unsigned long long *p)
+{
+    return __hip_atomic_load(p, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Waits (bounded) until *p >= target; false on time-out or a raised error.
+__device__ __forceinline__ bool sync_wait(GridSync *sync, unsigned long long *p, unsigned long long target)
+{
+    unsigned long spins = 0;
+    while (sync_load(p) < target) {
+        __builtin_amdgcn_s_sleep(1);
+        if (++spins > (1ul << 22) || sync_load(&sync->error.v)) {
+            atomicAdd(&sync->error.v, 1ull);
+            return false;
+        }
+    }
+    return true;
+}
+
+// Barrier number k (= passed) of a launch: two-level arrival, see GridSync.
 __device__ bool grid_barrier(GridSync *sync, unsigned long long nblocks, unsigned long long &passed)
 {
     __syncthreads();
     __shared__ int ok;
     if (threadIdx.x == 0) {
-        ok = 1;
-        const unsigned long long target = (passed + 1) * nblocks;
+        const unsigned long long k1 = passed + 1;
+        const unsigned long long ngroups = (nblocks + kBarrierGroup - 1) / kBarrierGroup;
+        const unsigned long long g = blockIdx.x / kBarrierGroup;
+        const unsigned long long gsize = min((unsigned long long)kBarrierGroup, nblocks - g * kBarrierGroup);
+        bool good = true;
         __threadfence();
-        atomicAdd(&sync->count, 1ull);
-        unsigned long spins = 0;
-        while (__hip_atomic_load(&sync->count, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) < target) {
-            __builtin_amdgcn_s_sleep(1);
-            if (++spins > (1ul << 22) ||
-                __hip_atomic_load(&sync->error, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) {
-                atomicOr(&sync->error, 1u);
-                ok = 0;
-                break;
-            }
+        const unsigned long long old = atomicAdd(&sync->arrive[g].v, 1ull);
+        if (old + 1 == k1 * gsize) {
+            atomicAdd(&sync->top.v, 1ull);
+            good = sync_wait(sync, &sync->top.v, k1 * ngroups);
+            atomicAdd(&sync->release[g].v, 1ull);
+        } else {
+            good = sync_wait(sync, &sync->release[g].v, k1);
         }
         __threadfence();
+        ok = good ? 1 : 0;
     }
     passed += 1;
     __syncthreads();
@@ -1083,7 +1100,10 @@ hipError_t launch_persistent(int fmt, const RepDesc *descs, RepState *st, const 
 {
     void *args[] = {(void *)&descs, (void *)&st, (void *)&wm, (void *)&nm, (void *)&ws, (void *)&ns,
                     (void *)&reps, (void *)&nreps, (void *)&nsweeps, (void *)&sync};
-    hipLaunchKernelGGL(k_zero_u64, dim3(1), dim3(64), 0, s, (unsigned long long *)&sync->count, 1L);
+    // fresh barrier counters for this launch (the error line is kept)
+    hipLaunchKernelGGL(k_zero_u64, dim3(1), dim3(64), 0, s, (unsigned long long *)&sync->top, 16L);
+    hipLaunchKernelGGL(k_zero_u64, dim3(64), dim3(256), 0, s, (unsigned long long *)&sync->arrive[0],
+                       (long)(2 * kMaxGroups * 16));
     const hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     return hipLaunchCooperativeKernel(persistent_kernel(fmt), dim3(grid), dim3(kBlock), args, 0, s);

@@ -110,6 +110,7 @@ def lib():
             "islf_get_tile": [vp, i32, P(i32)],
             "islf_set_tile": [vp, i32, i32],
             "islf_autotune": [vp, u32],
+            "islf_phase_timings": [vp, u32, vp, vp],
         }
         for name, args in sig.items():
             f = getattr(L, name)
@@ -286,6 +287,14 @@ class Context:
 
     def autotune(self, sweeps=4):
         _check(lib().islf_autotune(self._h, sweeps))
+
+    def phase_timings(self, n_sweeps=4):
+        """Mean ms per launch and launch counts of (main phase, seam phase, end of sweep)."""
+        ms = np.zeros(3, dtype=np.float64)
+        cnt = np.zeros(3, dtype=np.uint32)
+        _check(lib().islf_phase_timings(self._h, n_sweeps, ms.ctypes.data_as(C.c_void_p),
+                                        cnt.ctypes.data_as(C.c_void_p)))
+        return ms, cnt
 
 
 def num_tiles(spin_format=INT8) -> int:

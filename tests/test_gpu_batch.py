@@ -89,3 +89,16 @@ def test_graph_invalidated_by_membership_change():
         with pytest.raises(islf.IslfError) as e:
             ctx.replay(1)
         assert e.value.status == islf.ESTATE
+
+
+def test_phase_timings_are_real_sweeps():
+    ps = batch_params()
+    with islf.Context([islf.Replica(**p) for p in ps], obs_capacity=32) as ctx:
+        ms, cnt = ctx.phase_timings(3)
+        ctx.sweep(2)
+        recs = [ctx.measure(i, 0, 5) for i in range(len(ps))]
+    assert list(cnt) == [6, 6, 3]
+    assert (ms > 0).all()
+    for i, p in enumerate(ps):
+        _, o_rec, _ = oracle_trajectory(p, 5)
+        assert np.array_equal(recs[i], o_rec)
