@@ -59,6 +59,9 @@ def parse():
     ap.add_argument("--no-extras", action="store_true", help="skip the other forms and formats")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--cpu-sweeps", type=int, default=3)
+    ap.add_argument("--serve", type=int, default=0, metavar="N",
+                    help="instead: the serving workload, N Poisson requests (20/s, log-uniform sizes)")
+    ap.add_argument("--serve-budget-mib", type=int, default=256)
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of MIB MiB (traffic counter calibration)")
     return ap.parse_args()
@@ -160,6 +163,22 @@ def main():
         b.copy_(a)
         torch.cuda.synchronize()
         print(json.dumps({"calibration_copy_bytes": n}), flush=True)
+        return
+
+    if args.serve:
+        from paper_1411_5588_amd import serving
+        reqs = serving.poisson_workload(args.serve, rate=20.0)
+        srv = serving.Server(budget_bytes=args.serve_budget_mib << 20, max_slots=64, spin_format=islf.BITPACK,
+                             max_step=50, obs_capacity=5000, realtime=True)
+        try:
+            srv.run(reqs)
+        finally:
+            srv.close()
+        s = serving.summary(reqs, srv.wall_s, srv.busy_s)
+        print(json.dumps({"metric": "serving", "workload": f"{args.serve} requests, Poisson 20/s, sites "
+                          f"log-uniform on [1e5, 4.6e7], T~U[2,4.2], h1~U[0.1,1], hn=-h1, sweeps~U{{500..5000}}, "
+                          f"bit-packed, memory budget {args.serve_budget_mib} MiB",
+                          **{k: round(v, 4) for k, v in s.items()}}), flush=True)
         return
 
     Lx, Ly, Lz = SHAPE

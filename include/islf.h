@@ -170,6 +170,10 @@ islf_status islf_energy(islf_ctx *ctx, int32_t rep, uint64_t first, uint32_t cou
  * synchronises.  Errors: ERANGE if a replica lacks a requested record. */
 islf_status islf_means(islf_ctx *ctx, uint64_t first, uint32_t count, double *out);
 
+/* The same means for one replica: out[0..4] = mean {E, B, M, M1, Mn} over
+ * its records first .. first+count-1.  Host out; synchronises. */
+islf_status islf_replica_means(islf_ctx *ctx, int32_t rep, uint64_t first, uint32_t count, double *out);
+
 /* ---------------------------------------------------------------------- */
 /* Thermodynamic integration over the surface field (Eq. 9, Eq. 22)        */
 /* ---------------------------------------------------------------------- */

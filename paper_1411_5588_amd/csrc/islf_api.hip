@@ -977,11 +977,131 @@ extern "C" islf_status islf_set_tile(islf_ctx *ctx, int32_t rep, int32_t tile)
     return ISLF_OK;
 }
 
+// Times one tile variant for one size class: the class's replicas sweep
+// `sweeps` times through kernels launched on their own work lists (events on
+// the context stream).  Spins, records and state are restored afterwards by
+// the caller.
+static islf_status time_variant(islf_ctx *c, const std::vector<int> &cls, int tile, uint32_t sweeps, double *ms)
+{
+    std::vector<Entry> M, S;
+    for (int r : cls) {
+        Replica &R = c->reps[r];
+        R.tile = tile;
+        build_work(R, r, c->fmt);
+        M.insert(M.end(), R.main.begin(), R.main.end());
+        S.insert(S.end(), R.seam.begin(), R.seam.end());
+        HIP_TRY(hipMemcpyAsync(c->d_desc + r, &R.d, sizeof(RepDesc), hipMemcpyHostToDevice, c->stream));
+    }
+    long long slot = 0;
+    for (Entry &e : M) { e.slot0 = slot; slot += e.nsteps; }
+    slot = 0;
+    for (Entry &e : S) { e.slot0 = slot; slot += e.nsteps; }
+    Entry *dm = (Entry *)dev_alloc(c, sizeof(Entry) * M.size());
+    Entry *ds = (Entry *)dev_alloc(c, sizeof(Entry) * S.size());
+    int *dl = (int *)dev_alloc(c, sizeof(int) * cls.size());
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    hipError_t err = (dm && ds && dl) ? hipSuccess : hipErrorOutOfMemory;
+    if (err == hipSuccess) err = hipEventCreate(&e0);
+    if (err == hipSuccess) err = hipEventCreate(&e1);
+    if (err == hipSuccess) err = hipMemcpyAsync(dm, M.data(), sizeof(Entry) * M.size(), hipMemcpyHostToDevice, c->stream);
+    if (err == hipSuccess) err = hipMemcpyAsync(ds, S.data(), sizeof(Entry) * S.size(), hipMemcpyHostToDevice, c->stream);
+    if (err == hipSuccess) err = hipMemcpyAsync(dl, cls.data(), sizeof(int) * cls.size(), hipMemcpyHostToDevice, c->stream);
+    for (uint32_t k = 0; k <= sweeps && err == hipSuccess; ++k) {
+        if (k == 1) err = hipEventRecord(e0, c->stream);   // sweep 0 warms up
+        for (int p = 0; p < 4 && err == hipSuccess; ++p)
+            err = launch_phase(c->fmt, c->d_desc, c->d_state, p >= 2 ? ds : dm, p >= 2 ? (long)S.size() : (long)M.size(),
+                               p, c->max_grid, c->stream);
+        if (err == hipSuccess) err = launch_end_sweep(c->d_desc, c->d_state, dl, (int)cls.size(), c->stream);
+    }
+    if (err == hipSuccess) err = hipEventRecord(e1, c->stream);
+    if (err == hipSuccess) err = hipStreamSynchronize(c->stream);
+    float t = 0.f;
+    if (err == hipSuccess) err = hipEventElapsedTime(&t, e0, e1);
+    if (e0) (void)hipEventDestroy(e0);
+    if (e1) (void)hipEventDestroy(e1);
+    dev_free(c, dm);
+    dev_free(c, ds);
+    dev_free(c, dl);
+    if (err != hipSuccess) return fail(ISLF_EDEVICE, "autotune trial failed: %s", hipGetErrorString(err));
+    *ms = t;
+    return ISLF_OK;
+}
+
 extern "C" islf_status islf_autotune(islf_ctx *ctx, uint32_t sweeps)
 {
-    (void)ctx;
-    (void)sweeps;
-    return fail(ISLF_ESTATE, "autotune not available yet");
+    if (!ctx) return fail(ISLF_EINVAL, "NULL context");
+    if (sweeps < 1) return fail(ISLF_EINVAL, "sweeps must be >= 1");
+    islf_status st = sync_tables(ctx);
+    if (st != ISLF_OK) return st;
+    HIP_TRY(hipStreamSynchronize(ctx->stream));
+    // size classes: replicas of one shape share a variant
+    std::vector<std::vector<int>> classes;
+    for (int r : ctx->live) {
+        bool placed = false;
+        for (auto &cl : classes) {
+            const islf_replica_desc &a = ctx->reps[cl[0]].desc, &b = ctx->reps[r].desc;
+            if (a.Lx == b.Lx && a.Ly == b.Ly && a.Lz == b.Lz) {
+                cl.push_back(r);
+                placed = true;
+                break;
+            }
+        }
+        if (!placed) classes.push_back({r});
+    }
+    // back up every live replica's memory block and state
+    std::vector<void *> backup(ctx->reps.size(), nullptr);
+    RepState *st_backup = (RepState *)dev_alloc(ctx, sizeof(RepState) * ctx->slot_capacity);
+    islf_status result = st_backup ? ISLF_OK : fail(ISLF_ENOMEM, "cannot back up replica state");
+    for (int r : ctx->live) {
+        if (result != ISLF_OK) break;
+        Replica &R = ctx->reps[r];
+        backup[r] = dev_alloc(ctx, R.mem_bytes);
+        if (!backup[r]) result = fail(ISLF_ENOMEM, "cannot back up replica %d", r);
+        else if (hipMemcpyAsync(backup[r], R.mem, R.mem_bytes, hipMemcpyDeviceToDevice, ctx->stream) != hipSuccess)
+            result = fail(ISLF_EDEVICE, "backup copy failed");
+    }
+    if (result == ISLF_OK &&
+        hipMemcpyAsync(st_backup, ctx->d_state, sizeof(RepState) * ctx->slot_capacity, hipMemcpyDeviceToDevice,
+                       ctx->stream) != hipSuccess)
+        result = fail(ISLF_EDEVICE, "state backup failed");
+    auto restore = [&]() -> islf_status {
+        for (int r : ctx->live)
+            HIP_TRY(hipMemcpyAsync(ctx->reps[r].mem, backup[r], ctx->reps[r].mem_bytes, hipMemcpyDeviceToDevice,
+                                   ctx->stream));
+        HIP_TRY(hipMemcpyAsync(ctx->d_state, st_backup, sizeof(RepState) * ctx->slot_capacity,
+                               hipMemcpyDeviceToDevice, ctx->stream));
+        return ISLF_OK;
+    };
+    for (auto &cl : classes) {
+        if (result != ISLF_OK) break;
+        const int orig = ctx->reps[cl[0]].tile;
+        double best = 1e300;
+        int best_tile = orig;
+        for (int tile = 0; tile < num_tiles_of(ctx->fmt) && result == ISLF_OK; ++tile) {
+            double ms = 0;
+            result = time_variant(ctx, cl, tile, sweeps, &ms);
+            if (result == ISLF_OK) result = restore();
+            if (result == ISLF_OK && ms < best) {
+                best = ms;
+                best_tile = tile;
+            }
+        }
+        for (int r : cl) {
+            ctx->reps[r].tile = (result == ISLF_OK) ? best_tile : orig;
+            build_work(ctx->reps[r], r, ctx->fmt);
+        }
+    }
+    if (result == ISLF_OK) {
+        islf_status rs = restore();
+        if (rs != ISLF_OK) result = rs;
+    }
+    if (hipStreamSynchronize(ctx->stream) != hipSuccess && result == ISLF_OK)
+        result = fail(ISLF_EDEVICE, "autotune synchronisation failed");
+    for (void *b : backup) dev_free(ctx, b);
+    dev_free(ctx, st_backup);
+    ctx->dirty = true;
+    if (result != ISLF_OK) return result;
+    return sync_tables(ctx);
 }
 
 extern "C" islf_status islf_phase_timings(islf_ctx *ctx, uint32_t n_sweeps, double *mean_ms, uint32_t *launches)
@@ -1038,5 +1158,25 @@ extern "C" islf_status islf_phase_timings(islf_ctx *ctx, uint32_t n_sweeps, doub
         mean_ms[k] = cnt[k] ? sum[k] / cnt[k] : 0.0;
         launches[k] = cnt[k];
     }
+    return ISLF_OK;
+}
+
+extern "C" islf_status islf_replica_means(islf_ctx *ctx, int32_t rep, uint64_t first, uint32_t count, double *out)
+{
+    islf_status st = check_rep(ctx, rep);
+    if (st != ISLF_OK) return st;
+    if (!out) return fail(ISLF_EINVAL, "NULL output");
+    st = check_records(ctx, rep, first, count);
+    if (st != ISLF_OK) return st;
+    int *dl = (int *)dev_alloc(ctx, sizeof(int));
+    double *tmp = (double *)dev_alloc(ctx, sizeof(double) * 5);
+    hipError_t e = (dl && tmp) ? hipSuccess : hipErrorOutOfMemory;
+    if (e == hipSuccess) e = hipMemcpyAsync(dl, &rep, sizeof(int), hipMemcpyHostToDevice, ctx->stream);
+    if (e == hipSuccess) e = launch_means(ctx->d_desc, dl, 1, first, count, tmp, ctx->stream);
+    if (e == hipSuccess) e = hipMemcpyAsync(out, tmp, sizeof(double) * 5, hipMemcpyDeviceToHost, ctx->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(ctx->stream);
+    dev_free(ctx, dl);
+    dev_free(ctx, tmp);
+    if (e != hipSuccess) return fail(ISLF_EDEVICE, "replica means failed: %s", hipGetErrorString(e));
     return ISLF_OK;
 }

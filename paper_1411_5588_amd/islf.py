@@ -111,6 +111,7 @@ def lib():
             "islf_set_tile": [vp, i32, i32],
             "islf_autotune": [vp, u32],
             "islf_phase_timings": [vp, u32, vp, vp],
+            "islf_replica_means": [vp, i32, u64, u32, vp],
         }
         for name, args in sig.items():
             f = getattr(L, name)
@@ -259,6 +260,12 @@ class Context:
         _check(lib().islf_num_replicas(self._h, C.byref(n)))
         out = np.zeros((n.value, 5), dtype=np.float64)
         _check(lib().islf_means(self._h, first, count, out.ctypes.data_as(C.c_void_p)))
+        return out
+
+    def replica_means(self, rep, first, count) -> np.ndarray:
+        """mean (E, B, M, M1, Mn) of one replica's records first .. first+count-1."""
+        out = np.zeros(5, dtype=np.float64)
+        _check(lib().islf_replica_means(self._h, rep, first, count, out.ctypes.data_as(C.c_void_p)))
         return out
 
     # batching / graphs / tuning -------------------------------------------
