@@ -12,8 +12,9 @@ timing starts; nothing is copied to the host inside the timed region.
 Prints one JSON line.  Besides the headline (bit-packed spins, batched form)
 it reports the int8 format and the plain one-lattice-per-launch and
 persistent forms on the same workload, the roofline of the dominant kernel
-(the main-phase update kernel, timed live with HIP events on the context's
-stream) and the CPU oracle timed on a bounded sample of the same workload.
+(the sweep kernel: its A and B launches, timed live with HIP events on the
+context's stream) and the CPU oracle timed on a bounded sample of the same
+workload.
 """
 from __future__ import annotations
 
@@ -44,7 +45,7 @@ HBM_PEAK_GBS = 8000.0
 # sum, 1 compare against the tabulated threshold, 1 select of the flip).
 OPS_PER_UPDATE = 17
 BYTES_PER_UPDATE = {"int8": 2.0, "bitpack": 0.25}   # each spin read and written once per sweep
-PROFILE_TRAFFIC = os.path.join(ROOT, "profiles", "traffic_main_phase_160x480x600x3.md")
+PROFILE_TRAFFIC = os.path.join(ROOT, "profiles", "traffic_sweep_kernel_160x480x600x3.md")
 KERNEL_SOURCE = os.path.join(ROOT, "paper_1411_5588_amd", "csrc", "islf_kernels.hip")
 
 
@@ -102,7 +103,7 @@ def run_form(islf, torch, form, fmt, steps, warmup, chunk, timings=False):
         out = dict(ms_per_sweep=total_ms / steps, sweeps_per_launch=chunk, launches=n_launch)
         if timings:
             ms, cnt = ctx.phase_timings(8)
-            out["kernel_ms"] = {"main_phase": float(ms[0]), "seam_phase": float(ms[1]), "end_of_sweep": float(ms[2])}
+            out["kernel_ms"] = {"A": float(ms[0]), "B": float(ms[1]), "close": float(ms[2])}
             out["kernel_launches"] = [int(c) for c in cnt]
         return out
     finally:
@@ -115,8 +116,9 @@ def kernel_source_hash():
 
 
 def committed_traffic(fmt):
-    """HBM bytes per main-phase dispatch from the committed counter summary,
-    or None when the kernel source has changed since it was taken."""
+    """HBM bytes per sweep-kernel dispatch (mean of the A and B launches) from
+    the committed counter summary, or None when the kernel source has changed
+    since it was taken."""
     try:
         text = open(PROFILE_TRAFFIC).read()
     except OSError:
@@ -199,15 +201,18 @@ def main():
             forms[f"{form}_{fmt}"] = round(updates_per_sweep / (r["ms_per_sweep"] * 1e6), 2)
             print(f"# {form}/{fmt}: {r}", file=sys.stderr, flush=True)
 
-    # dominant kernel: the main-phase update kernel; one launch updates the
-    # sites of one main phase (rows y >= 1, one parity) of all replicas
-    main_ms = main_run["kernel_ms"]["main_phase"]
-    updates_per_launch = n_reps * Lx * (Ly - 1) * Lz / 2
+    # dominant kernel: the sweep kernel.  Its A and B launches of one sweep
+    # together update every site of every replica once (A: phase 0 and the
+    # previous sweep's phase 3, B: phases 1 and 2), so a launch updates half
+    # a sweep on average; the per-launch time is the mean of the A and B times
+    kms = main_run["kernel_ms"]
+    main_ms = 0.5 * (kms["A"] + kms["B"])
+    updates_per_launch = n_reps * N / 2
     achieved_tops = OPS_PER_UPDATE * updates_per_launch / (main_ms * 1e-3) / 1e12
     traffic = committed_traffic(args.fmt)
     roofline = {"bound": "alu", "achieved": round(achieved_tops, 2), "peak": round(VALU_PEAK_TOPS, 1),
                 "unit": "T int-op/s", "frac": round(achieved_tops / VALU_PEAK_TOPS, 4), "traffic": traffic,
-                "kernel": "main-phase update", "kernel_ms": round(main_ms, 5),
+                "kernel": "k_sweep (A and B launches)", "kernel_ms": round(main_ms, 5),
                 "ops_per_update": OPS_PER_UPDATE,
                 "hbm_view": {"algorithmic_GBs": round(BYTES_PER_UPDATE[args.fmt] * updates_per_launch
                                                       / (main_ms * 1e-3) / 1e9, 1),

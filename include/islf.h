@@ -62,10 +62,15 @@ typedef enum { ISLF_SPIN_INT8 = 0, ISLF_SPIN_BITPACK = 1 } islf_spin_format;
 typedef enum { ISLF_INIT_RANDOM = 0, ISLF_INIT_UP = 1, ISLF_INIT_DOWN = 2, ISLF_INIT_HOST = 3 } islf_init;
 
 /* How islf_sweep issues work.  All forms give bit-identical results.
- *  PLAIN      : one launch per replica per phase (one lattice per launch).
- *  BATCHED    : one launch per phase covering every replica.
- *  PERSISTENT : one launch for all requested sweeps of every replica; the
- *               phases are separated by device-side barriers. */
+ * A run of k sweeps is issued as launches A(0) B(0) A(1) B(1) ... B(k-1) F:
+ * A(s) does phase 3 of sweep s-1 on row y = 0 (s > 0) and phase 0 of sweep
+ * s, B(s) phases 1 and 2 of sweep s, F phase 3 of the last sweep, then a
+ * small fold launch closes the run's last record.
+ *  PLAIN      : the A and B launches go one replica at a time (one lattice
+ *               per launch).
+ *  BATCHED    : each A and B launch covers every replica.
+ *  PERSISTENT : one launch for all requested sweeps of every replica, with
+ *               device-side grid barriers in place of the launch boundaries. */
 typedef enum { ISLF_EXEC_PLAIN = 0, ISLF_EXEC_BATCHED = 1, ISLF_EXEC_PERSISTENT = 2 } islf_exec;
 
 /* One replica (Sec. II.A Eq. 1 parameters plus the Markov-chain identity).
@@ -229,12 +234,13 @@ islf_status islf_get_tile(const islf_ctx *ctx, int32_t rep, int32_t *tile);
 islf_status islf_set_tile(islf_ctx *ctx, int32_t rep, int32_t tile);
 islf_status islf_autotune(islf_ctx *ctx, uint32_t sweeps);
 
-/* Runs n_sweeps sweeps of every live replica one kernel at a time (batched
- * form, no graph) with HIP events around each launch on the context's stream,
- * and returns the mean duration in milliseconds and the launch count of each
- * kernel kind: [0] main phases (rows y >= 1), [1] seam phases (row y = 0),
- * [2] end-of-sweep bookkeeping.  The sweeps are real (they advance the
- * chains).  Synchronises.  Errors: EINVAL, EDEVICE, ERANGE. */
+/* Runs n_sweeps sweeps of every live replica in the batched form (no graph)
+ * with HIP events around each launch on the context's stream, and returns
+ * the mean duration in milliseconds and the launch count of each kind:
+ * [0] A launches (phase 3 of the previous sweep on row 0, phase 0),
+ * [1] B launches (phases 1 and 2), [2] the closing F + fold pair of the run.
+ * The sweeps are real (they advance the chains).  Synchronises.
+ * Errors: EINVAL, EDEVICE, ERANGE. */
 islf_status islf_phase_timings(islf_ctx *ctx, uint32_t n_sweeps, double *mean_ms, uint32_t *launches);
 
 /* Thread-local message describing the last failure on this thread. */

@@ -17,12 +17,14 @@
 #include "islf_internal.h"
 
 namespace islf {
-hipError_t launch_phase(int fmt, const RepDesc *descs, const RepState *st, const Entry *work, long n,
-                        int phase, int grid, hipStream_t s);
-hipError_t launch_end_sweep(const RepDesc *descs, RepState *st, const int *reps, int n, hipStream_t s);
+hipError_t launch_sweep(int fmt, int kind, const RepDesc *descs, RepState *st, const Entry *slabw, long n_slab,
+                        const Entry *mainw, long n_main, const int *reps, int n_reps, uint32_t s, uint32_t flags,
+                        hipStream_t strm);
+hipError_t launch_fold(const RepDesc *descs, RepState *st, const int *reps, int n_reps, uint32_t s,
+                       uint32_t advance, hipStream_t strm);
 const void *persistent_kernel(int fmt);
-hipError_t launch_persistent(int fmt, const RepDesc *descs, RepState *st, const Entry *wm, long nm,
-                             const Entry *ws, long ns, const int *reps, int nreps, uint32_t nsweeps,
+hipError_t launch_persistent(int fmt, const RepDesc *descs, RepState *st, const Entry *ws, long ns,
+                             const Entry *wm, long nm, const int *reps, int nreps, uint32_t nsweeps,
                              GridSync *sync, int grid, hipStream_t s);
 hipError_t launch_init(int fmt, const RepDesc *descs, int rep, int mode, const int8_t *host, hipStream_t s);
 hipError_t launch_export(const RepDesc *descs, int rep, int8_t *out, hipStream_t s);
@@ -66,12 +68,13 @@ static islf_status fail(islf_status st, const char *fmt, ...)
 extern "C" const char *islf_last_error(void) { return g_err.c_str(); }
 
 // ---------------------------------------------------------------------------
-// tile variants (main phases, both formats): a workgroup owns tj columns x ty
-// rows (tj*ty <= 256 threads) and each thread marches through mx x planes;
-// a column is an 8-byte chunk (int8) or a 32-bit word of a sublattice row
-// (bit-packed), and tj is the most even split of a row's columns into pieces
-// of at most tj_max.  Seam phases (row y = 0): 2^lj_seam columns x the rest
-// of the 256 threads in x, one column each.
+// tile variants (main tiles, rows 2 .. Ly-2, both formats): a workgroup owns
+// tj columns x ty rows (tj*ty <= 256 threads) and each thread marches through
+// mx x planes; a column is an 8-byte chunk (int8) or a 32-bit word of a
+// sublattice row (bit-packed), and tj is the most even split of a row's
+// columns into pieces of at most tj_max.  Seam-slab tiles (rows Ly-1, 0, 1):
+// np mirror pairs of x planes x nj columns with np*nj <= 128, so that a row
+// stage has at most one task per thread.
 // ---------------------------------------------------------------------------
 struct I8Tile {
     int tj_max, mx;
@@ -100,7 +103,7 @@ static I8Shape i8_shape(const islf_replica_desc &d, int tile, int fmt = ISLF_SPI
     const long pieces = ceil_div(C, t.tj_max);
     I8Shape s;
     s.tj = (int)ceil_div(C, pieces);
-    s.ty = (int)std::min<long>(kBlock / s.tj, std::max(1, d.Ly - 1));
+    s.ty = (int)std::min<long>(kBlock / s.tj, std::max(1, d.Ly - 3));
     s.mx = std::min(t.mx, d.Lx);
     return s;
 }
@@ -108,7 +111,8 @@ static I8Shape i8_shape(const islf_replica_desc &d, int tile, int fmt = ISLF_SPI
 // fraction of thread-steps that touch a real chunk / word
 static double tile_efficiency(const islf_replica_desc &d, int fmt, int tile)
 {
-    const double ny = d.Ly - 1;
+    const double ny = d.Ly - 3;
+    if (ny <= 0) return 1.0;
     const long C = fmt == ISLF_SPIN_INT8 ? (d.Lz + 7) / 8 : (d.Lz + 63) / 64;
     const I8Shape s = i8_shape(d, tile, fmt);
     const double entries = (double)ceil_div(d.Lx, s.mx) * ceil_div((long)ny, s.ty) * ceil_div(C, s.tj);
@@ -131,20 +135,31 @@ static int default_tile(const islf_replica_desc *d, int fmt)
     return best_i;
 }
 
-static int seam_lj(const islf_replica_desc &d, int fmt)
+struct SlabShape {
+    int np, nj;
+};
+// the (pairs, columns) split with the fewest idle thread slots, then the
+// fewest entries
+static SlabShape slab_shape(const islf_replica_desc &d, int fmt)
 {
     const long J = fmt == ISLF_SPIN_INT8 ? (d.Lz + 7) / 8 : (d.Lz + 63) / 64;
-    double best = -1.0;
-    int best_lj = 0;
-    for (int lj = 0; lj <= 8; ++lj) {
-        const long tj = 1l << lj, tx = 1l << (8 - lj);
-        const double eff = (double)d.Lx * J / ((double)ceil_div(d.Lx, tx) * tx * ceil_div(J, tj) * tj);
-        if (eff > best + 1e-9) {
-            best = eff;
-            best_lj = lj;
+    const long P = (d.Lx + 1) / 2;
+    const long cap = kBlock / 2;
+    SlabShape best{1, 1};
+    long best_cost = -1;
+    for (long pieces = ceil_div(J, cap); pieces <= J; ++pieces) {
+        const long nj = ceil_div(J, pieces);
+        if (ceil_div(J, nj) != pieces) continue;
+        const long np0 = std::min(P, std::max(1l, cap / nj));
+        const long np = ceil_div(P, ceil_div(P, np0));
+        const long entries = ceil_div(P, np) * pieces;
+        const long cost = entries * cap;   // thread slots of one row stage
+        if (best_cost < 0 || cost < best_cost) {
+            best_cost = cost;
+            best = SlabShape{(int)np, (int)nj};
         }
     }
-    return best_lj;
+    return best;
 }
 
 // ---------------------------------------------------------------------------
@@ -158,7 +173,7 @@ struct Replica {
     uint64_t t_host = 0;     // sweeps issued so far
     int tile = 0;
     RepDesc d{};
-    std::vector<Entry> main, seam;
+    std::vector<Entry> main, slab;
 };
 
 struct islf_ctx {
@@ -181,10 +196,10 @@ struct islf_ctx {
     unsigned long long *d_scratch = nullptr;   // 64 x u64
     int *d_live = nullptr;                      // live replica ids
     int live_capacity = 0;
-    Entry *d_main = nullptr, *d_seam = nullptr;
-    long main_cap = 0, seam_cap = 0;
-    std::vector<long> main_off, main_len, seam_off, seam_len;  // per slot, within the device lists
-    long n_main = 0, n_seam = 0;
+    Entry *d_main = nullptr, *d_slab = nullptr;
+    long main_cap = 0, slab_cap = 0;
+    std::vector<long> main_off, main_len, slab_off, slab_len;  // per slot, within the device lists
+    long n_main = 0, n_slab = 0;
     std::vector<int> live;
     bool dirty = true;
 
@@ -286,36 +301,21 @@ static void build_work(Replica &R, int rep_id, int fmt)
 {
     const islf_replica_desc &d = R.desc;
     R.main.clear();
-    R.seam.clear();
+    R.slab.clear();
     const int J = fmt == ISLF_SPIN_INT8 ? (d.Lz + 7) / 8 : (d.Lz + 63) / 64;
-    if (fmt == ISLF_SPIN_INT8) {
-        const I8Shape s = i8_shape(d, R.tile);
-        for (int x0 = 0; x0 < d.Lx; x0 += s.mx)
-            for (int y0 = 1; y0 < d.Ly; y0 += s.ty)
-                for (int j0 = 0; j0 < J; j0 += s.tj)
-                    R.main.push_back(Entry{rep_id, x0, y0, j0, std::min(s.mx, d.Lx - x0), 0, 0});
-        R.d.i8_tj = s.tj;
-        R.d.i8_ty = s.ty;
-        R.d.i8_mx = s.mx;
-        R.d.tile_lj = 0;
-        R.d.tile_ly = 0;
-    } else {
-        const I8Shape s = i8_shape(d, R.tile, fmt);
-        for (int x0 = 0; x0 < d.Lx; x0 += s.mx)
-            for (int y0 = 1; y0 < d.Ly; y0 += s.ty)
-                for (int j0 = 0; j0 < J; j0 += s.tj)
-                    R.main.push_back(Entry{rep_id, x0, y0, j0, std::min(s.mx, d.Lx - x0), 0, 0});
-        R.d.i8_tj = s.tj;
-        R.d.i8_ty = s.ty;
-        R.d.i8_mx = s.mx;
-        R.d.tile_lj = 0;
-        R.d.tile_ly = 0;
-    }
-    const int lj = seam_lj(d, fmt);
-    const int tjs = 1 << lj, txs = 1 << (8 - lj);
-    for (int x0 = 0; x0 < d.Lx; x0 += txs)
-        for (int j0 = 0; j0 < J; j0 += tjs) R.seam.push_back(Entry{rep_id, x0, 0, j0, 1, 0, 0});
-    R.d.tile_lj_seam = lj;
+    const I8Shape s = i8_shape(d, R.tile, fmt);
+    for (int x0 = 0; x0 < d.Lx; x0 += s.mx)
+        for (int y0 = 2; y0 < d.Ly - 1; y0 += s.ty)
+            for (int j0 = 0; j0 < J; j0 += s.tj)
+                R.main.push_back(Entry{rep_id, x0, y0, j0, std::min(s.mx, d.Lx - x0), 0, 0});
+    R.d.i8_tj = s.tj;
+    R.d.i8_ty = s.ty;
+    R.d.i8_mx = s.mx;
+    const SlabShape sl = slab_shape(d, fmt);
+    const int P = (d.Lx + 1) / 2;
+    for (int p0 = 0; p0 < P; p0 += sl.np)
+        for (int j0 = 0; j0 < J; j0 += sl.nj)
+            R.slab.push_back(Entry{rep_id, p0, std::min(sl.np, P - p0), j0, std::min(sl.nj, J - j0), 0, 0});
 }
 
 static void fill_desc(Replica &R, int fmt, uint32_t cap)
@@ -382,7 +382,7 @@ static islf_status sync_tables(islf_ctx *c)
     std::vector<Entry> M, S;
     const int n = (int)c->reps.size();
     c->main_off.assign(n, 0); c->main_len.assign(n, 0);
-    c->seam_off.assign(n, 0); c->seam_len.assign(n, 0);
+    c->slab_off.assign(n, 0); c->slab_len.assign(n, 0);
     for (int i = 0; i < n; ++i) {
         Replica &R = c->reps[i];
         if (!R.live) continue;
@@ -390,17 +390,12 @@ static islf_status sync_tables(islf_ctx *c)
         c->main_off[i] = (long)M.size();
         c->main_len[i] = (long)R.main.size();
         M.insert(M.end(), R.main.begin(), R.main.end());
-        c->seam_off[i] = (long)S.size();
-        c->seam_len[i] = (long)R.seam.size();
-        S.insert(S.end(), R.seam.begin(), R.seam.end());
+        c->slab_off[i] = (long)S.size();
+        c->slab_len[i] = (long)R.slab.size();
+        S.insert(S.end(), R.slab.begin(), R.slab.end());
     }
     long long slot = 0;
     for (Entry &e : M) {
-        e.slot0 = slot;
-        slot += e.nsteps;
-    }
-    slot = 0;
-    for (Entry &e : S) {
         e.slot0 = slot;
         slot += e.nsteps;
     }
@@ -410,11 +405,11 @@ static islf_status sync_tables(islf_ctx *c)
         c->d_main = (Entry *)dev_alloc(c, sizeof(Entry) * c->main_cap);
         if (!c->d_main) return fail(ISLF_ENOMEM, "cannot allocate work list");
     }
-    if ((long)S.size() > c->seam_cap) {
-        dev_free(c, c->d_seam);
-        c->seam_cap = std::max<long>((long)S.size(), 2 * c->seam_cap);
-        c->d_seam = (Entry *)dev_alloc(c, sizeof(Entry) * c->seam_cap);
-        if (!c->d_seam) return fail(ISLF_ENOMEM, "cannot allocate work list");
+    if ((long)S.size() > c->slab_cap) {
+        dev_free(c, c->d_slab);
+        c->slab_cap = std::max<long>((long)S.size(), 2 * c->slab_cap);
+        c->d_slab = (Entry *)dev_alloc(c, sizeof(Entry) * c->slab_cap);
+        if (!c->d_slab) return fail(ISLF_ENOMEM, "cannot allocate work list");
     }
     if ((int)c->live.size() > c->live_capacity) {
         dev_free(c, c->d_live);
@@ -423,7 +418,7 @@ static islf_status sync_tables(islf_ctx *c)
         if (!c->d_live) return fail(ISLF_ENOMEM, "cannot allocate live list");
     }
     if (!M.empty()) HIP_TRY(hipMemcpyAsync(c->d_main, M.data(), sizeof(Entry) * M.size(), hipMemcpyHostToDevice, c->stream));
-    if (!S.empty()) HIP_TRY(hipMemcpyAsync(c->d_seam, S.data(), sizeof(Entry) * S.size(), hipMemcpyHostToDevice, c->stream));
+    if (!S.empty()) HIP_TRY(hipMemcpyAsync(c->d_slab, S.data(), sizeof(Entry) * S.size(), hipMemcpyHostToDevice, c->stream));
     if (!c->live.empty())
         HIP_TRY(hipMemcpyAsync(c->d_live, c->live.data(), sizeof(int) * c->live.size(), hipMemcpyHostToDevice, c->stream));
     for (int i = 0; i < n; ++i) {
@@ -432,7 +427,7 @@ static islf_status sync_tables(islf_ctx *c)
     }
     HIP_TRY(hipStreamSynchronize(c->stream));
     c->n_main = (long)M.size();
-    c->n_seam = (long)S.size();
+    c->n_slab = (long)S.size();
     c->dirty = false;
     c->graph_valid = false;
     return ISLF_OK;
@@ -511,7 +506,7 @@ static void destroy_ctx(islf_ctx *c)
     dev_free(c, c->d_scratch);
     dev_free(c, c->d_live);
     dev_free(c, c->d_main);
-    dev_free(c, c->d_seam);
+    dev_free(c, c->d_slab);
     delete c;
 }
 
@@ -671,33 +666,67 @@ extern "C" islf_status islf_set_exec(islf_ctx *ctx, int32_t mode)
     return ISLF_OK;
 }
 
+// Enqueues n >= 1 sweeps of the replicas in the device list dl (nl ids) in
+// the batched form, over the given slab and main lists: A(s) B(s) for each
+// sweep, then F and the closing fold.  Optional events bracket each launch
+// (A and B of sweep s at ev[4s..4s+3], F + fold at ev[4n], ev[4n+1]).
+static hipError_t enqueue_batched(islf_ctx *c, const Entry *ws, long ns, const Entry *wm, long nm, const int *dl,
+                                  int nl, uint32_t n, hipEvent_t *ev = nullptr)
+{
+    hipError_t e = hipSuccess;
+    auto mark = [&](size_t i) {
+        if (ev && e == hipSuccess) e = hipEventRecord(ev[i], c->stream);
+    };
+    for (uint32_t s = 0; s < n && e == hipSuccess; ++s) {
+        mark(4 * (size_t)s);
+        if (e == hipSuccess)
+            e = launch_sweep(c->fmt, KIND_A, c->d_desc, c->d_state, ws, ns, wm, nm, dl, nl, s, s ? FLAG_PREV : 0u,
+                             c->stream);
+        mark(4 * (size_t)s + 1);
+        mark(4 * (size_t)s + 2);
+        if (e == hipSuccess)
+            e = launch_sweep(c->fmt, KIND_B, c->d_desc, c->d_state, ws, ns, wm, nm, dl, nl, s, s ? FLAG_FOLD : 0u,
+                             c->stream);
+        mark(4 * (size_t)s + 3);
+    }
+    mark(4 * (size_t)n);
+    if (e == hipSuccess)
+        e = launch_sweep(c->fmt, KIND_F, c->d_desc, c->d_state, ws, ns, wm, nm, dl, nl, n - 1, 0u, c->stream);
+    if (e == hipSuccess) e = launch_fold(c->d_desc, c->d_state, dl, nl, n - 1, n, c->stream);
+    mark(4 * (size_t)n + 1);
+    return e;
+}
+
 // Enqueues n sweeps in the context's execution form (no checks, no sync).
 static islf_status enqueue_sweeps(islf_ctx *c, uint32_t n)
 {
     const int nl = (int)c->live.size();
     if (nl == 0 || n == 0) return ISLF_OK;
     if (c->exec == ISLF_EXEC_PERSISTENT) {
-        hipError_t e = launch_persistent(c->fmt, c->d_desc, c->d_state, c->d_main, c->n_main, c->d_seam, c->n_seam,
+        hipError_t e = launch_persistent(c->fmt, c->d_desc, c->d_state, c->d_slab, c->n_slab, c->d_main, c->n_main,
                                          c->d_live, nl, n, c->d_sync, c->persistent_grid, c->stream);
         if (e != hipSuccess) return fail(ISLF_EDEVICE, "persistent launch failed: %s", hipGetErrorString(e));
         return ISLF_OK;
     }
-    for (uint32_t s = 0; s < n; ++s) {
-        for (int p = 0; p < 4; ++p) {
-            const bool seam = p >= 2;
-            if (c->exec == ISLF_EXEC_BATCHED) {
-                HIP_TRY(launch_phase(c->fmt, c->d_desc, c->d_state, seam ? c->d_seam : c->d_main,
-                                     seam ? c->n_seam : c->n_main, p, c->max_grid, c->stream));
-            } else {
-                for (int r : c->live) {
-                    const Entry *w = seam ? c->d_seam + c->seam_off[r] : c->d_main + c->main_off[r];
-                    const long len = seam ? c->seam_len[r] : c->main_len[r];
-                    HIP_TRY(launch_phase(c->fmt, c->d_desc, c->d_state, w, len, p, c->max_grid, c->stream));
-                }
-            }
-        }
-        HIP_TRY(launch_end_sweep(c->d_desc, c->d_state, c->d_live, nl, c->stream));
+    if (c->exec == ISLF_EXEC_BATCHED) {
+        HIP_TRY(enqueue_batched(c, c->d_slab, c->n_slab, c->d_main, c->n_main, c->d_live, nl, n));
+        return ISLF_OK;
     }
+    // plain: one lattice per launch; replica r's fold list is its entry in d_live
+    for (uint32_t s = 0; s < n; ++s)
+        for (int k = 0; k < 2; ++k)
+            for (int li = 0; li < nl; ++li) {
+                const int r = c->live[li];
+                HIP_TRY(launch_sweep(c->fmt, k, c->d_desc, c->d_state, c->d_slab + c->slab_off[r], c->slab_len[r],
+                                     c->d_main + c->main_off[r], c->main_len[r], c->d_live + li, 1, s,
+                                     s ? (k == 0 ? FLAG_PREV : FLAG_FOLD) : 0u, c->stream));
+            }
+    for (int li = 0; li < nl; ++li) {
+        const int r = c->live[li];
+        HIP_TRY(launch_sweep(c->fmt, KIND_F, c->d_desc, c->d_state, c->d_slab + c->slab_off[r], c->slab_len[r],
+                             c->d_main + c->main_off[r], c->main_len[r], c->d_live + li, 1, n - 1, 0u, c->stream));
+    }
+    HIP_TRY(launch_fold(c->d_desc, c->d_state, c->d_live, nl, n - 1, n, c->stream));
     return ISLF_OK;
 }
 
@@ -876,7 +905,7 @@ extern "C" islf_status islf_footprint_bytes(const islf_replica_desc *desc, int32
     R.desc = *desc;
     R.tile = default_tile(desc, spin_format);
     build_work(R, 0, spin_format);
-    *bytes = replica_bytes(desc, spin_format, obs_capacity) + sizeof(Entry) * (R.main.size() + R.seam.size()) +
+    *bytes = replica_bytes(desc, spin_format, obs_capacity) + sizeof(Entry) * (R.main.size() + R.slab.size()) +
              sizeof(RepDesc) + sizeof(RepState);
     return ISLF_OK;
 }
@@ -989,30 +1018,27 @@ static islf_status time_variant(islf_ctx *c, const std::vector<int> &cls, int ti
         R.tile = tile;
         build_work(R, r, c->fmt);
         M.insert(M.end(), R.main.begin(), R.main.end());
-        S.insert(S.end(), R.seam.begin(), R.seam.end());
+        S.insert(S.end(), R.slab.begin(), R.slab.end());
         HIP_TRY(hipMemcpyAsync(c->d_desc + r, &R.d, sizeof(RepDesc), hipMemcpyHostToDevice, c->stream));
     }
     long long slot = 0;
     for (Entry &e : M) { e.slot0 = slot; slot += e.nsteps; }
-    slot = 0;
-    for (Entry &e : S) { e.slot0 = slot; slot += e.nsteps; }
-    Entry *dm = (Entry *)dev_alloc(c, sizeof(Entry) * M.size());
+    Entry *dm = (Entry *)dev_alloc(c, sizeof(Entry) * std::max<size_t>(1, M.size()));
     Entry *ds = (Entry *)dev_alloc(c, sizeof(Entry) * S.size());
     int *dl = (int *)dev_alloc(c, sizeof(int) * cls.size());
     hipEvent_t e0 = nullptr, e1 = nullptr;
     hipError_t err = (dm && ds && dl) ? hipSuccess : hipErrorOutOfMemory;
     if (err == hipSuccess) err = hipEventCreate(&e0);
     if (err == hipSuccess) err = hipEventCreate(&e1);
-    if (err == hipSuccess) err = hipMemcpyAsync(dm, M.data(), sizeof(Entry) * M.size(), hipMemcpyHostToDevice, c->stream);
+    if (err == hipSuccess && !M.empty())
+        err = hipMemcpyAsync(dm, M.data(), sizeof(Entry) * M.size(), hipMemcpyHostToDevice, c->stream);
     if (err == hipSuccess) err = hipMemcpyAsync(ds, S.data(), sizeof(Entry) * S.size(), hipMemcpyHostToDevice, c->stream);
     if (err == hipSuccess) err = hipMemcpyAsync(dl, cls.data(), sizeof(int) * cls.size(), hipMemcpyHostToDevice, c->stream);
-    for (uint32_t k = 0; k <= sweeps && err == hipSuccess; ++k) {
-        if (k == 1) err = hipEventRecord(e0, c->stream);   // sweep 0 warms up
-        for (int p = 0; p < 4 && err == hipSuccess; ++p)
-            err = launch_phase(c->fmt, c->d_desc, c->d_state, p >= 2 ? ds : dm, p >= 2 ? (long)S.size() : (long)M.size(),
-                               p, c->max_grid, c->stream);
-        if (err == hipSuccess) err = launch_end_sweep(c->d_desc, c->d_state, dl, (int)cls.size(), c->stream);
-    }
+    // one warm-up sweep, then the timed run
+    if (err == hipSuccess) err = enqueue_batched(c, ds, (long)S.size(), dm, (long)M.size(), dl, (int)cls.size(), 1);
+    if (err == hipSuccess) err = hipEventRecord(e0, c->stream);
+    if (err == hipSuccess)
+        err = enqueue_batched(c, ds, (long)S.size(), dm, (long)M.size(), dl, (int)cls.size(), sweeps);
     if (err == hipSuccess) err = hipEventRecord(e1, c->stream);
     if (err == hipSuccess) err = hipStreamSynchronize(c->stream);
     float t = 0.f;
@@ -1113,43 +1139,27 @@ extern "C" islf_status islf_phase_timings(islf_ctx *ctx, uint32_t n_sweeps, doub
     st = check_sweep_range(ctx, n_sweeps);
     if (st != ISLF_OK) return st;
     const int nl = (int)ctx->live.size();
-    const int per_sweep = 5;
-    std::vector<hipEvent_t> ev(2 * per_sweep * (size_t)n_sweeps, nullptr);
+    std::vector<hipEvent_t> ev(4 * (size_t)n_sweeps + 2, nullptr);
     for (auto &e : ev)
         if (hipEventCreate(&e) != hipSuccess) {
             for (auto &f : ev)
                 if (f) (void)hipEventDestroy(f);
             return fail(ISLF_EDEVICE, "cannot create events");
         }
-    hipError_t err = hipSuccess;
-    for (uint32_t s = 0; s < n_sweeps && err == hipSuccess; ++s) {
-        for (int p = 0; p < 4 && err == hipSuccess; ++p) {
-            const bool seam = p >= 2;
-            hipEvent_t *e = &ev[2 * (per_sweep * (size_t)s + p)];
-            err = hipEventRecord(e[0], ctx->stream);
-            if (err == hipSuccess)
-                err = launch_phase(ctx->fmt, ctx->d_desc, ctx->d_state, seam ? ctx->d_seam : ctx->d_main,
-                                   seam ? ctx->n_seam : ctx->n_main, p, ctx->max_grid, ctx->stream);
-            if (err == hipSuccess) err = hipEventRecord(e[1], ctx->stream);
-        }
-        hipEvent_t *e = &ev[2 * (per_sweep * (size_t)s + 4)];
-        if (err == hipSuccess) err = hipEventRecord(e[0], ctx->stream);
-        if (err == hipSuccess) err = launch_end_sweep(ctx->d_desc, ctx->d_state, ctx->d_live, nl, ctx->stream);
-        if (err == hipSuccess) err = hipEventRecord(e[1], ctx->stream);
-    }
+    hipError_t err = nl ? enqueue_batched(ctx, ctx->d_slab, ctx->n_slab, ctx->d_main, ctx->n_main, ctx->d_live, nl,
+                                          n_sweeps, ev.data())
+                        : hipSuccess;
     if (err == hipSuccess) err = hipStreamSynchronize(ctx->stream);
     double sum[3] = {0, 0, 0};
     uint32_t cnt[3] = {0, 0, 0};
-    if (err == hipSuccess) {
-        for (uint32_t s = 0; s < n_sweeps; ++s)
-            for (int k = 0; k < per_sweep; ++k) {
-                float ms = 0.f;
-                hipEvent_t *e = &ev[2 * (per_sweep * (size_t)s + k)];
-                if (hipEventElapsedTime(&ms, e[0], e[1]) != hipSuccess) continue;
-                const int kind = k < 2 ? 0 : (k < 4 ? 1 : 2);
-                sum[kind] += ms;
-                cnt[kind] += 1;
-            }
+    if (err == hipSuccess && nl) {
+        for (size_t k = 0; k <= 2 * (size_t)n_sweeps; ++k) {
+            float ms = 0.f;
+            if (hipEventElapsedTime(&ms, ev[2 * k], ev[2 * k + 1]) != hipSuccess) continue;
+            const int kind = k == 2 * (size_t)n_sweeps ? 2 : (int)(k & 1);
+            sum[kind] += ms;
+            cnt[kind] += 1;
+        }
     }
     for (auto &e : ev) (void)hipEventDestroy(e);
     if (err != hipSuccess) return fail(ISLF_EDEVICE, "timed sweeps failed: %s", hipGetErrorString(err));

@@ -17,17 +17,24 @@ constexpr int kThrEntries = kClasses * kThrPerClass;
 constexpr int kPadEntry = kThrEntries - 1;   // class 3, u = 1, cnt = 7: never a real site
 constexpr int kMaxMarch = 256;       // x planes one thread may march through per entry
 
-// One tile of work for one replica: a box of rows/columns starting at
-// (x0, y0, j0) whose extent is the replica's tile shape.  j counts 8-byte
-// chunks (int8 format) or 32-bit words of one sublattice row (bit-packed).
-// A marching tile covers nsteps x planes from x0; the entries of one phase
-// list number their steps consecutively from slot0, so that a fixed grid can
-// split a list evenly at step granularity.
+// One tile of work for one replica.  j counts 8-byte chunks (int8 format) or
+// 32-bit words of one sublattice row (bit-packed).
+// Main tile (rows 2 .. Ly-2): a box of rows/columns starting at (x0, y0, j0)
+// whose extent is the replica's tile shape, marched through nsteps x planes
+// from x0; the entries of a main list number their steps consecutively from
+// slot0, so that a fixed grid can split a list evenly at step granularity.
+// Seam-slab tile (rows Ly-1, 0, 1): x0 = first x pair p (planes p and
+// Lx-1-p), y0 = number of consecutive pairs, j0 = first column,
+// nsteps = number of columns.
 struct Entry {
     int32_t rep, x0, y0, j0;
     int32_t nsteps, pad_;
     long long slot0;
 };
+
+// Launch kinds of a run of sweeps and their flags.
+enum { KIND_A = 0, KIND_B = 1, KIND_F = 2 };
+enum { FLAG_PREV = 1, FLAG_FOLD = 2 };   // A: do the previous sweep's phase 3; B: fold its record
 
 // Read-only description of a replica as the kernels see it.
 struct RepDesc {
@@ -46,11 +53,8 @@ struct RepDesc {
     int32_t seam_reflect;  // 1: the y seam maps x -> Lx-1-x
     int32_t seam_invert;   // 1: the y seam carries eps = -1
     uint32_t key0, key1, replica, cap;
-    int32_t tile_lj, tile_ly;      // bit-packed main phases: log2 tile extent along j and y
-    int32_t tile_lj_seam;          // seam phases: log2 tile extent along j
     int32_t fmt;                   // islf_spin_format
-    int32_t i8_tj, i8_ty, i8_mx;   // int8 main phases: chunks x rows per workgroup, x planes marched
-    int32_t pad_[1];
+    int32_t i8_tj, i8_ty, i8_mx;   // main tiles: columns x rows per workgroup, x planes marched
     double J, H, h1, hn;           // for energies (Eq. 1)
 };
 

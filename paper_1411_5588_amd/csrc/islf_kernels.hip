@@ -125,13 +125,12 @@ struct RepView {
     uint32_t Lzp;           // int8 row stride in bytes
     int seam_reflect, seam_invert;
     uint32_t key0, key1, replica, t;
-    int lj, ly;
-    int tj, ty, mx;          // int8 marching tile
+    int tj, ty, mx;          // marching tile
     bool never;              // some move can never be accepted (thr == 0)
 };
 
 __device__ __forceinline__ RepView load_view(const RepDesc *__restrict__ descs, const RepState *__restrict__ st,
-                                             int rep, bool seam, uint32_t t_offset)
+                                             int rep, uint32_t t_offset)
 {
     const RepDesc &d = descs[rep];
     RepView v;
@@ -143,8 +142,6 @@ __device__ __forceinline__ RepView load_view(const RepDesc *__restrict__ descs, 
     v.seam_invert = d.seam_invert;
     v.key0 = d.key0; v.key1 = d.key1; v.replica = d.replica;
     v.t = st[rep].t + t_offset;
-    v.lj = seam ? d.tile_lj_seam : d.tile_lj;
-    v.ly = seam ? 0 : d.tile_ly;
     v.tj = d.i8_tj;
     v.ty = d.i8_ty;
     v.mx = d.i8_mx;
@@ -312,7 +309,9 @@ __device__ __forceinline__ void bp_update_word(const RepView &v, int x, int y, i
     const uint64_t *tc = sthr + cls * kThrPerClass;
     const uint32_t gbase = row * (uint32_t)C + 8u * (uint32_t)w;
     uint32_t F = 0;
-#pragma unroll
+    // not unrolled: this path is a small share of the work and must not raise
+    // the register count of the kernels it is inlined into
+#pragma unroll 1
     for (int g4 = 0; g4 < 8; ++g4) {
         uint32_t rnd[4];
         philox10(((gbase + g4) << 1) | (uint32_t)q, v.t, v.replica, 0u, v.key0, v.key1, rnd);
@@ -339,20 +338,11 @@ __device__ __forceinline__ void bp_update_word(const RepView &v, int x, int y, i
 }
 
 // ---------------------------------------------------------------------------
-// int8 format, main phases (rows y >= 1): a thread owns one chunk column
-// (x0..x1-1, y, j) of its tile and marches through the x planes.  The chunk of
-// plane x-1 (read before its update: only the other-parity bytes are used,
-// and those are not written in this phase) and of plane x+1 stay in
-// registers, so a step loads the next plane, the two y neighbours and the two
-// z-edge bytes.  The per-byte table index 4*(cnt + 8u + 16*class) is formed
-// with word-wide adds; a shift by 8q moves the four sites of the phase to
-// bytes 0, 2, 4, 6.  A flip adds its packed (dB, dM) change to a register sum.
+// int8 format, main tiles.
 // ---------------------------------------------------------------------------
 struct MarchLane {
-    uint32_t oc, oym, oprev, onext;   // offsets inside the current x plane
-    uint32_t dyp;                     // change per x step of the y+1 neighbour's offset
-    uint64_t inv_p;                   // seam sign of the y+1 neighbour
-    uint64_t valid, padidx;           // short last chunk: real bytes / padding index
+    uint32_t oc, oym, oyp, oprev, onext;   // offsets inside the current x plane
+    uint64_t valid, padidx;                // short last chunk: real bytes / padding index
     int r;
 };
 
@@ -363,18 +353,18 @@ struct StepIn {
 };
 
 __device__ __forceinline__ StepIn load_step(const RepView &v, const MarchLane &L, const gcu8 *base, int x,
-                                            uint32_t oyp, uint32_t xstride)
+                                            uint32_t xstride)
 {
     StepIn in;
     in.Wn = (x + 1 < v.Lx) ? *(gcu64 *)(base + xstride + L.oc) : 0ull;
-    in.Yp = ld64(v.spins, oyp) ^ L.inv_p;
+    in.Yp = *(gcu64 *)(base + L.oyp);
     in.Ym = *(gcu64 *)(base + L.oym);
     in.pb = *(base + L.oprev);
     in.nb = *(base + L.onext);
     return in;
 }
 
-// int8 format, main phases (rows y >= 1): a thread owns one chunk column
+// int8 format, main tiles (rows 2 .. Ly-2): a thread owns one chunk column
 // (x0..x1-1, y, j) of its tile and marches through the x planes.  The chunk of
 // plane x-1 (read before its update: only its other-parity bytes are used,
 // and those are not written in this phase) and of plane x+1 stay in
@@ -393,7 +383,7 @@ __device__ __forceinline__ void i8_march(const RepView &v, const Entry &en, int 
     const int tj = tid - ty * v.tj;
     const int y = en.y0 + ty;
     const int j = en.j0 + tj;
-    if (ty >= v.ty || y >= v.Ly || j >= v.C) return;
+    if (ty >= v.ty || y >= v.Ly - 1 || j >= v.C) return;   // main rows are 2 .. Ly-2
     const int Lx = v.Lx, Ly = v.Ly, C = v.C, Lz = v.Lz;
     const uint32_t Lzp = v.Lzp;
     const int x0 = en.x0 + k_lo;
@@ -407,19 +397,9 @@ __device__ __forceinline__ void i8_march(const RepView &v, const Entry &en, int 
     const uint32_t yrow = (uint32_t)y * Lzp;
     L.oc = yrow + jo;
     L.oym = L.oc - Lzp;
+    L.oyp = L.oc + Lzp;
     L.oprev = (j > 0) ? L.oc - 1u : yrow + (uint32_t)(Lz - 1);
     L.onext = last ? yrow : L.oc + 8u;
-    L.inv_p = 0;
-    uint32_t oyp;
-    if (y < Ly - 1) {
-        oyp = (uint32_t)x0 * xstride + L.oc + Lzp;
-        L.dyp = xstride;
-    } else {
-        const uint32_t xs0 = v.seam_reflect ? (uint32_t)(Lx - 1 - x0) : (uint32_t)x0;
-        oyp = xs0 * xstride + jo;
-        L.dyp = v.seam_reflect ? (uint32_t)(0u - xstride) : xstride;
-        L.inv_p = v.seam_invert ? kOnes8 : 0ull;
-    }
     L.valid = (L.r == 8) ? ~0ull : ((1ull << (8 * L.r)) - 1ull);
     L.padidx = ~L.valid & (0x0101010101010101ull * (uint64_t)(4 * kPadEntry));
 
@@ -430,13 +410,13 @@ __device__ __forceinline__ void i8_march(const RepView &v, const Entry &en, int 
 
     uint64_t Wc = *(gcu64 *)(base + L.oc);
     uint64_t Wm = (x0 > 0) ? *(gcu64 *)(base - xstride + L.oc) : 0ull;
-    StepIn cur = load_step(v, L, base, x0, oyp, xstride);
+    StepIn cur = load_step(v, L, base, x0, xstride);
     int dsum = 0, d1 = 0, dn = 0;
     for (int x = x0; x < x1; ++x) {
         // next step's neighbours first: independent of this step's result
         StepIn nxt;
         const bool more = x + 1 < x1;
-        if (more) nxt = load_step(v, L, base + xstride, x + 1, oyp + L.dyp, xstride);
+        if (more) nxt = load_step(v, L, base + xstride, x + 1, xstride);
         uint64_t cnt = ((Wc << 8) | (uint64_t)cur.pb) + ((Wc >> 8) | ((uint64_t)cur.nb << (8 * (L.r - 1))));
         cnt += cur.Yp + cur.Ym;
         cnt += Wm + cur.Wn;
@@ -471,7 +451,6 @@ __device__ __forceinline__ void i8_march(const RepView &v, const Entry &en, int 
         Wc = cur.Wn;
         if (more) cur = nxt;
         base += xstride;
-        oyp += L.dyp;
         g += gstep;
         g ^= 1u;
         q ^= 1;
@@ -495,7 +474,7 @@ __device__ __forceinline__ uint32_t spread_nibbles(uint32_t x)
     return x;
 }
 
-// bit-packed format, main phases (rows y >= 1): a thread owns word w of its
+// bit-packed format, main tiles (rows 2 .. Ly-2): a thread owns word w of its
 // row's sublattices and marches through the x planes; at plane x it updates
 // the sublattice of the phase's parity (it alternates with x).  Neighbour
 // counts are bit-sliced; the 4-bit table index 8u + cnt of every site is
@@ -509,7 +488,7 @@ __device__ __forceinline__ void bp_march(const RepView &v, const Entry &en, int 
     const int tj = tid - ty * v.tj;
     const int y = en.y0 + ty;
     const int w = en.j0 + tj;
-    if (ty >= v.ty || y >= v.Ly || w >= v.Wq) return;
+    if (ty >= v.ty || y >= v.Ly - 1 || w >= v.Wq) return;   // main rows are 2 .. Ly-2
     const int Lx = v.Lx, Ly = v.Ly, C = v.C, Wq = v.Wq;
     const int nbits = v.Lz >> 1;
     const uint32_t RW = 2u * (uint32_t)Wq;
@@ -518,7 +497,6 @@ __device__ __forceinline__ void bp_march(const RepView &v, const Entry &en, int 
     gu32 *wout = (gu32 *)v.spins;
     const int nb_here = min(32, nbits - 32 * w);
     const uint32_t vmask = nb_here >= 32 ? 0xFFFFFFFFu : ((1u << nb_here) - 1u);
-    const uint32_t seam_mask = v.seam_invert ? 0xFFFFFFFFu : 0u;
     const int wl = (nbits - 1) >> 5, bl = (nbits - 1) & 31;   // last bit of a sublattice row
     const int x0 = en.x0 + k_lo;
     const int x1 = min(en.x0 + k_hi, Lx);
@@ -545,13 +523,7 @@ __device__ __forceinline__ void bp_march(const RepView &v, const Entry &en, int 
             zm = O;
             zp = (O >> 1) | (inb << (lastw ? (nb_here - 1) : 31));
         }
-        uint32_t yp;
-        if (y < Ly - 1) {
-            yp = *(gcu32 *)(words + own + RW);
-        } else {
-            const uint32_t xs = v.seam_reflect ? (uint32_t)(Lx - 1 - x) : (uint32_t)x;
-            yp = *(gcu32 *)(words + xs * (uint32_t)Ly * RW + (uint32_t)(q * Wq + w)) ^ seam_mask;
-        }
+        const uint32_t yp = *(gcu32 *)(words + own + RW);
         const uint32_t ym = *(gcu32 *)(words + own - RW);
         const uint32_t xm = (x > 0) ? *(gcu32 *)(words + own - xstride) : 0u;
         const uint32_t xp = (x < Lx - 1) ? *(gcu32 *)(words + own + xstride) : 0u;
@@ -608,126 +580,184 @@ __device__ __forceinline__ void bp_march(const RepView &v, const Entry &en, int 
 // ---------------------------------------------------------------------------
 // Processing of a contiguous range of work entries by one workgroup.
 // ---------------------------------------------------------------------------
-template <int FMT, bool SEAM>
-__device__ __forceinline__ void process_slots(const RepDesc *__restrict__ descs, const RepState *__restrict__ st,
-                                              const Entry *__restrict__ work, long n_entries, long e_begin,
-                                              long long s0, long long s1, int parity, uint32_t t_offset,
-                                              Tables *tb)
+// ---------------------------------------------------------------------------
+// Sweep schedule.  The four phases of sweep t run in two launches:
+//   A(t): phase 3 of sweep t-1 on row 0, then phase 0 of sweep t;
+//   B(t): phase 1 of sweep t, then phase 2 of sweep t on row 0;
+// and a final launch F runs phase 3 of the last sweep.  Rows 2 .. Ly-2 are
+// done by main (marching) tiles.  Rows Ly-1, 0 and 1 belong to seam-slab
+// tiles: a slab tile owns a set of x planes closed under x -> Lx-1-x and a
+// range of z columns, and runs its two stages with one workgroup barrier in
+// between.  Every input a stage reads is either written earlier by the same
+// workgroup or not written by anybody during that launch:
+//  - phase 3 (row 0) reads row-0 phase-2 sites (written only in B) and rows
+//    1 / Ly-1 before this launch's phase 0 (whose sites it shares rows with
+//    are updated by the same slab tile, after the barrier);
+//  - phase 0 on rows 1 / Ly-1 reads row 0 at the same z and x or Lx-1-x,
+//    both in the tile, after its phase-3 stage;
+//  - phase 1 on rows 1 / Ly-1 reads row-0 phase-2 sites before their update
+//    (same tile, later stage) and phase-0 sites (not written in B);
+//  - phase 2 on row 0 reads rows 1 / Ly-1 after the tile's phase-1 stage.
+// Main tiles never read row 0.  The record of sweep t-1 is folded by block 0
+// of B(t) (all of its phases are complete by then; B(t) only adds to the
+// other accumulator half), the last sweep's by the last block of F.
+// A slab entry is (rep, first x pair, number of pairs, first column,
+// number of columns) in the fields (rep, x0, y0, j0, nsteps).
+// ---------------------------------------------------------------------------
+// One wave folds the spread partial sums of sweep t of one replica into its
+// running observables and record (slots read and cleared atomically).
+__device__ __forceinline__ void fold_sweep(const RepDesc &d, RepState &sr, uint32_t t, int lane)
 {
-    const bool seam = SEAM;
-    Acc a = {0, 0, 0, 0};
-    int cur_rep = -1;
-    RepView v;
-    for (long e = e_begin; e < n_entries; ++e) {
-        const Entry en = work[e];
-        if (en.slot0 >= s1) break;
-        const int k_lo = (int)max(0ll, s0 - en.slot0);
-        const int k_hi = (int)min((long long)en.nsteps, s1 - en.slot0);
-        if (k_lo >= k_hi) continue;
-        if (en.rep != cur_rep) {
-            if (cur_rep >= 0) flush_acc(a, v.acc, v.t, blockIdx.x & (kAccSlots - 1));
-            cur_rep = en.rep;
-            v = load_view(descs, st, cur_rep, seam, t_offset);
-            load_tables(descs[cur_rep], tb);
-            __syncthreads();
-        }
-        if (FMT == ISLF_SPIN_INT8 && !seam) {
-            const bool ragged = (v.Lz & 7) != 0;
-            if (v.never) {
-                if (ragged) i8_march<true, true>(v, en, k_lo, k_hi, parity, tb, a);
-                else i8_march<true, false>(v, en, k_lo, k_hi, parity, tb, a);
-            } else {
-                if (ragged) i8_march<false, true>(v, en, k_lo, k_hi, parity, tb, a);
-                else i8_march<false, false>(v, en, k_lo, k_hi, parity, tb, a);
-            }
-            continue;
-        }
-        if (FMT == ISLF_SPIN_BITPACK && !seam) {
-            if (v.never) bp_march<true>(v, en, k_lo, k_hi, parity, tb, a);
-            else bp_march<false>(v, en, k_lo, k_hi, parity, tb, a);
-            continue;
-        }
-        const int tid = threadIdx.x;
-        const int j = en.j0 + (tid & ((1 << v.lj) - 1));
-        const int y = en.y0 + ((tid >> v.lj) & ((1 << v.ly) - 1));
-        const int x = en.x0 + (tid >> (v.lj + v.ly));
-        const int jmax = (FMT == ISLF_SPIN_INT8) ? v.C : v.Wq;
-        const bool inside = (x < v.Lx) && (j < jmax) && (seam ? (y == 0) : (y < v.Ly));
-        if (inside) {
-            if (FMT == ISLF_SPIN_INT8) i8_update_chunk(v, x, y, j, parity, tb->thr, a);
-            else bp_update_word(v, x, y, j, parity, tb->thr, a);
-        }
-    }
-    if (cur_rep >= 0) flush_acc(a, v.acc, v.t, blockIdx.x & (kAccSlots - 1));
-}
-
-// First entry of a phase list whose steps reach past slot s (binary search).
-__device__ __forceinline__ long find_entry(const Entry *__restrict__ work, long n, long long s)
-{
-    long lo = 0, hi = n;
-    while (lo < hi) {
-        const long mid = (lo + hi) >> 1;
-        const Entry en = work[mid];
-        if (en.slot0 + en.nsteps <= s) lo = mid + 1;
-        else hi = mid;
-    }
-    return lo;
-}
-
-// One phase of one sweep: workgroup b takes entry b whole (the hardware
-// dispatcher balances the load over the chip).
-template <int FMT, bool SEAM>
-__global__ __launch_bounds__(kBlock) void k_phase(const RepDesc *__restrict__ descs,
-                                                  const RepState *__restrict__ st,
-                                                  const Entry *__restrict__ work, long n_entries,
-                                                  int phase)
-{
-    __shared__ Tables tb;
-    const long b = blockIdx.x;
-    const Entry en = work[b];
-    process_slots<FMT, SEAM>(descs, st, work, b + 1, b, en.slot0, en.slot0 + en.nsteps, phase & 1, 0u, &tb);
-}
-
-// End of a sweep: fold the spread partial sums into the running observables,
-// store the record of sweep t, clear the accumulator and advance t.
-// One wave per listed replica.
-__global__ void k_end_sweep(const RepDesc *__restrict__ descs, RepState *__restrict__ st,
-                            const int *__restrict__ reps, int n)
-{
-    const int wave = (blockIdx.x * blockDim.x + threadIdx.x) >> 6;
-    const int lane = threadIdx.x & 63;
-    if (wave >= n) return;
-    const int r = reps[wave];
-    const RepDesc &d = descs[r];
-    const uint32_t t = st[r].t;
     long long *slot = d.acc + ((size_t)(t & 1) * kAccSlots + lane) * 4;
     long long v[4];
 #pragma unroll
-    for (int k = 0; k < 4; ++k) {
-        v[k] = slot[k];
-        slot[k] = 0;
-    }
+    for (int k = 0; k < 4; ++k) v[k] = (long long)atomicExch((unsigned long long *)&slot[k], 0ull);
 #pragma unroll
     for (int k = 0; k < 4; ++k) {
 #pragma unroll
         for (int off = 32; off > 0; off >>= 1) v[k] += __shfl_xor(v[k], off, 64);
     }
     if (lane == 0) {
-        RepState &s = st[r];
         islf_obs o;
-        o.B = s.cur[0] + v[0];
-        o.M = s.cur[1] + v[1];
-        o.M1 = s.cur[2] + v[2];
-        o.Mn = s.cur[3] + v[3];
-        s.cur[0] = o.B; s.cur[1] = o.M; s.cur[2] = o.M1; s.cur[3] = o.Mn;
+        o.B = sr.cur[0] + v[0];
+        o.M = sr.cur[1] + v[1];
+        o.M1 = sr.cur[2] + v[2];
+        o.Mn = sr.cur[3] + v[3];
+        sr.cur[0] = o.B; sr.cur[1] = o.M; sr.cur[2] = o.M1; sr.cur[3] = o.Mn;
         d.rec[t % d.cap] = o;
-        s.t = t + 1;
     }
 }
 
+// Wave w of the grid (blockIdx * 4 + wave) folds sweep st.t + s of the listed
+// replicas w, w + 4*grid, ...; with `advance` it then moves their sweep
+// counters on by that much.  Waves only: no workgroup barrier.
+__device__ __forceinline__ void fold_waves(const RepDesc *__restrict__ descs, RepState *__restrict__ st,
+                                           const int *__restrict__ reps, int n_reps, uint32_t s, uint32_t advance)
+{
+    const int lane = threadIdx.x & 63;
+    const int per_block = kBlock / 64;
+    for (int i = blockIdx.x * per_block + (threadIdx.x >> 6); i < n_reps; i += gridDim.x * per_block) {
+        const int r = reps[i];
+        fold_sweep(descs[r], st[r], st[r].t + s, lane);
+        if (advance && lane == 0) st[r].t += advance;
+    }
+}
+
+// Updates of one slab stage: `phase` decides the rows (0/1: rows 1 and Ly-1,
+// one row when Ly = 2; 2/3: row 0) and the parity; the x pairs and the
+// columns come from the entry.  Sites of one phase are never neighbours, so
+// the tasks of a stage are independent.
+template <int FMT>
+__device__ __forceinline__ void slab_stage(const RepView &v, const Entry &en, int phase, const Tables *tb, Acc &a)
+{
+    const int Lx = v.Lx, Ly = v.Ly;
+    const int p0 = en.x0, np = en.y0, j0 = en.j0, nj = en.nsteps;
+    const int rows = phase >= 2 ? 1 : (Ly == 2 ? 1 : 2);
+    const int nx = 2 * np;
+    const int ntask = rows * nx * nj;
+    for (int k = threadIdx.x; k < ntask; k += kBlock) {
+        const int jj = k % nj;
+        const int rest = k / nj;
+        const int xi = rest % nx, ri = rest / nx;
+        const int p = p0 + (xi >> 1);
+        const int x = (xi & 1) ? Lx - 1 - p : p;
+        if ((xi & 1) && x == p) continue;   // the middle plane of an odd Lx pairs with itself
+        const int y = phase >= 2 ? 0 : (ri == 0 ? 1 : Ly - 1);
+        if (FMT == ISLF_SPIN_INT8) i8_update_chunk(v, x, y, j0 + jj, phase & 1, tb->thr, a);
+        else bp_update_word(v, x, y, j0 + jj, phase & 1, tb->thr, a);
+    }
+}
+
+// One slab entry of launch KIND for sweep st.t + s; ends with a workgroup
+// barrier (in the last flush).
+template <int FMT, int KIND>
+__device__ __forceinline__ void slab_entry(const RepDesc *__restrict__ descs, const RepState *__restrict__ st,
+                                           const Entry &en, uint32_t s, uint32_t flags, Tables *tb)
+{
+    const RepView v = load_view(descs, st, en.rep, s);
+    load_tables(descs[en.rep], tb);
+    __syncthreads();
+    const int slot = blockIdx.x & (kAccSlots - 1);
+    Acc a = {0, 0, 0, 0};
+    if (KIND == KIND_A) {
+        if (flags & FLAG_PREV) {
+            RepView vp = v;
+            vp.t = v.t - 1;
+            slab_stage<FMT>(vp, en, 3, tb, a);
+            flush_acc(a, v.acc, vp.t, slot);   // its barrier also orders the two stages
+        }
+        slab_stage<FMT>(v, en, 0, tb, a);
+        flush_acc(a, v.acc, v.t, slot);
+    } else if (KIND == KIND_B) {
+        slab_stage<FMT>(v, en, 1, tb, a);
+        flush_acc(a, v.acc, v.t, slot);
+        slab_stage<FMT>(v, en, 2, tb, a);
+        flush_acc(a, v.acc, v.t, slot);
+    } else {
+        slab_stage<FMT>(v, en, 3, tb, a);
+        flush_acc(a, v.acc, v.t, slot);
+    }
+}
+
+// One main entry (rows 2 .. Ly-2), x steps [k_lo, k_hi), of launch A
+// (phase 0) or B (phase 1) of sweep st.t + s; ends with a workgroup barrier.
+template <int FMT, int KIND>
+__device__ __forceinline__ void main_entry(const RepDesc *__restrict__ descs, const RepState *__restrict__ st,
+                                           const Entry &en, int k_lo, int k_hi, uint32_t s, Tables *tb)
+{
+    const RepView v = load_view(descs, st, en.rep, s);
+    load_tables(descs[en.rep], tb);
+    __syncthreads();
+    Acc a = {0, 0, 0, 0};
+    const int parity = KIND == KIND_A ? 0 : 1;
+    if (FMT == ISLF_SPIN_INT8) {
+        const bool ragged = (v.Lz & 7) != 0;
+        if (v.never) {
+            if (ragged) i8_march<true, true>(v, en, k_lo, k_hi, parity, tb, a);
+            else i8_march<true, false>(v, en, k_lo, k_hi, parity, tb, a);
+        } else {
+            if (ragged) i8_march<false, true>(v, en, k_lo, k_hi, parity, tb, a);
+            else i8_march<false, false>(v, en, k_lo, k_hi, parity, tb, a);
+        }
+    } else {
+        if (v.never) bp_march<true>(v, en, k_lo, k_hi, parity, tb, a);
+        else bp_march<false>(v, en, k_lo, k_hi, parity, tb, a);
+    }
+    flush_acc(a, v.acc, v.t, blockIdx.x & (kAccSlots - 1));
+}
+
+// Launches A, B and F of sweep st.t + s.  Workgroups [0, n_slab) take one
+// slab entry each (first, so that the two-stage tiles start early), the rest
+// one main entry each (none in F).  With FLAG_FOLD, waves of B first fold
+// the previous sweep's record.
+template <int FMT, int KIND>
+__global__ __launch_bounds__(kBlock) void k_sweep(const RepDesc *__restrict__ descs, RepState *__restrict__ st,
+                                                  const Entry *__restrict__ slabw, long n_slab,
+                                                  const Entry *__restrict__ mainw, const int *__restrict__ reps,
+                                                  int n_reps, uint32_t s, uint32_t flags)
+{
+    __shared__ Tables tb;
+    const long b = blockIdx.x;
+    if (KIND == KIND_B && (flags & FLAG_FOLD)) fold_waves(descs, st, reps, n_reps, s - 1, 0u);
+    if (b < n_slab) {
+        slab_entry<FMT, KIND>(descs, st, slabw[b], s, flags, &tb);
+    } else if (KIND != KIND_F) {
+        const Entry en = mainw[b - n_slab];
+        main_entry<FMT, KIND>(descs, st, en, 0, en.nsteps, s, &tb);
+    }
+}
+
+// Closes a run of sweeps: folds sweep st.t + s and advances the counters.
+__global__ __launch_bounds__(kBlock) void k_fold(const RepDesc *__restrict__ descs, RepState *__restrict__ st,
+                                                 const int *__restrict__ reps, int n_reps, uint32_t s,
+                                                 uint32_t advance)
+{
+    fold_waves(descs, st, reps, n_reps, s, advance);
+}
+
 // ---------------------------------------------------------------------------
-// Persistent form: all sweeps of all replicas in one launch; phases are
-// separated by a grid-wide barrier with a bounded wait.
+// Persistent form: the same schedule inside one cooperative launch, with a
+// bounded two-level grid barrier in place of each launch boundary.
 // ---------------------------------------------------------------------------
 __device__ __forceinline__ unsigned long long sync_load(unsigned long long *p)
 {
@@ -776,67 +806,62 @@ __device__ bool grid_barrier(GridSync *sync, unsigned long long nblocks, unsigne
     return ok != 0;
 }
 
+// First main entry whose steps reach past slot s (binary search).
+__device__ __forceinline__ long find_entry(const Entry *__restrict__ work, long n, long long s)
+{
+    long lo = 0, hi = n;
+    while (lo < hi) {
+        const long mid = (lo + hi) >> 1;
+        const Entry en = work[mid];
+        if (en.slot0 + en.nsteps <= s) lo = mid + 1;
+        else hi = mid;
+    }
+    return lo;
+}
+
+// The work of one launch kind inside the persistent kernel: slab entries go
+// round robin, the main entries' x steps are split evenly over the grid.
+template <int FMT, int KIND>
+__device__ void persistent_part(const RepDesc *__restrict__ descs, const RepState *__restrict__ st,
+                                const Entry *__restrict__ slabw, long n_slab, const Entry *__restrict__ mainw,
+                                long n_main, uint32_t s, uint32_t flags, Tables *tb)
+{
+    const long G = gridDim.x, b = blockIdx.x;
+    for (long e = b; e < n_slab; e += G) slab_entry<FMT, KIND>(descs, st, slabw[e], s, flags, tb);
+    if (KIND == KIND_F || n_main == 0) return;
+    const Entry tail = mainw[n_main - 1];
+    const long long S = tail.slot0 + tail.nsteps;
+    const long long s0 = b * S / G, s1 = (b + 1) * S / G;
+    for (long e = find_entry(mainw, n_main, s0); e < n_main; ++e) {
+        const Entry en = mainw[e];
+        if (en.slot0 >= s1) break;
+        const int k_lo = (int)max(0ll, s0 - en.slot0);
+        const int k_hi = (int)min((long long)en.nsteps, s1 - en.slot0);
+        if (k_lo < k_hi) main_entry<FMT, KIND>(descs, st, en, k_lo, k_hi, s, tb);
+    }
+}
+
 template <int FMT>
 __global__ __launch_bounds__(kBlock) void k_persistent(const RepDesc *__restrict__ descs,
                                                        RepState *__restrict__ st,
-                                                       const Entry *__restrict__ work_main, long n_main,
-                                                       const Entry *__restrict__ work_seam, long n_seam,
+                                                       const Entry *__restrict__ slabw, long n_slab,
+                                                       const Entry *__restrict__ mainw, long n_main,
                                                        const int *__restrict__ reps, int n_reps,
                                                        uint32_t n_sweeps, GridSync *sync)
 {
     __shared__ Tables tb;
-    const long G = gridDim.x;
-    const long b = blockIdx.x;
+    const unsigned long long G = gridDim.x;
     unsigned long long passed = 0;
     for (uint32_t s = 0; s < n_sweeps; ++s) {
-        for (int p = 0; p < 4; ++p) {
-            // an even split of the phase's x steps over the fixed grid
-            const Entry *work = p >= 2 ? work_seam : work_main;
-            const long n = p >= 2 ? n_seam : n_main;
-            if (n > 0) {
-                const Entry tail = work[n - 1];
-                const long long S = tail.slot0 + tail.nsteps;
-                const long long s0 = b * S / G, s1 = (b + 1) * S / G;
-                const long eb = find_entry(work, n, s0);
-                if (p >= 2) process_slots<FMT, true>(descs, st, work, n, eb, s0, s1, p & 1, s, &tb);
-                else process_slots<FMT, false>(descs, st, work, n, eb, s0, s1, p & 1, s, &tb);
-            }
-            if (!grid_barrier(sync, (unsigned long long)G, passed)) return;
-        }
-        // bookkeeping of sweep s: replica i is folded by block i mod G while
-        // the other blocks go on with the next sweep (other accumulator half)
-        for (int i = (int)b; i < n_reps; i += (int)G) {
-            if (threadIdx.x < 64) {
-                const int lane = threadIdx.x;
-                const int r = reps[i];
-                const RepDesc &d = descs[r];
-                const uint32_t t = st[r].t + s;
-                long long *slot = d.acc + ((size_t)(t & 1) * kAccSlots + lane) * 4;
-                long long v[4];
-#pragma unroll
-                for (int k = 0; k < 4; ++k)
-                    v[k] = (long long)atomicExch((unsigned long long *)&slot[k], 0ull);
-#pragma unroll
-                for (int k = 0; k < 4; ++k) {
-#pragma unroll
-                    for (int off = 32; off > 0; off >>= 1) v[k] += __shfl_xor(v[k], off, 64);
-                }
-                if (lane == 0) {
-                    RepState &sr = st[r];
-                    islf_obs o;
-                    o.B = sr.cur[0] + v[0];
-                    o.M = sr.cur[1] + v[1];
-                    o.M1 = sr.cur[2] + v[2];
-                    o.Mn = sr.cur[3] + v[3];
-                    sr.cur[0] = o.B; sr.cur[1] = o.M; sr.cur[2] = o.M1; sr.cur[3] = o.Mn;
-                    d.rec[t % d.cap] = o;
-                }
-            }
-        }
+        persistent_part<FMT, KIND_A>(descs, st, slabw, n_slab, mainw, n_main, s, s ? FLAG_PREV : 0u, &tb);
+        if (!grid_barrier(sync, G, passed)) return;
+        if (s > 0) fold_waves(descs, st, reps, n_reps, s - 1, 0u);
+        persistent_part<FMT, KIND_B>(descs, st, slabw, n_slab, mainw, n_main, s, 0u, &tb);
+        if (!grid_barrier(sync, G, passed)) return;
     }
-    // every block has passed the last barrier: advance the sweep counters
-    if (!grid_barrier(sync, (unsigned long long)G, passed)) return;
-    for (int i = (int)b * kBlock + threadIdx.x; i < n_reps; i += (int)G * kBlock) st[reps[i]].t += n_sweeps;
+    persistent_part<FMT, KIND_F>(descs, st, slabw, n_slab, mainw, n_main, n_sweeps - 1, 0u, &tb);
+    if (!grid_barrier(sync, G, passed)) return;
+    fold_waves(descs, st, reps, n_reps, n_sweeps - 1, n_sweeps);
 }
 
 // ---------------------------------------------------------------------------
@@ -1063,28 +1088,44 @@ __global__ void k_integrate(const double *__restrict__ h, const double *__restri
 // ---------------------------------------------------------------------------
 // Host-callable launchers (used by islf_api.hip).
 // ---------------------------------------------------------------------------
-hipError_t launch_phase(int fmt, const RepDesc *descs, const RepState *st, const Entry *work, long n,
-                        int phase, int grid, hipStream_t s)
+template <int FMT>
+static void launch_sweep_fmt(int kind, unsigned int grid, const RepDesc *descs, RepState *st, const Entry *slabw,
+                             long n_slab, const Entry *mainw, const int *reps, int n_reps, uint32_t s,
+                             uint32_t flags, hipStream_t strm)
 {
-    if (n <= 0) return hipSuccess;
-    (void)grid;
-    const unsigned int blocks = (unsigned int)n;   // one entry per workgroup
-    const bool seam = phase >= 2;
-    if (fmt == ISLF_SPIN_INT8) {
-        if (seam) hipLaunchKernelGGL((k_phase<ISLF_SPIN_INT8, true>), dim3(blocks), dim3(kBlock), 0, s, descs, st, work, n, phase);
-        else hipLaunchKernelGGL((k_phase<ISLF_SPIN_INT8, false>), dim3(blocks), dim3(kBlock), 0, s, descs, st, work, n, phase);
-    } else {
-        if (seam) hipLaunchKernelGGL((k_phase<ISLF_SPIN_BITPACK, true>), dim3(blocks), dim3(kBlock), 0, s, descs, st, work, n, phase);
-        else hipLaunchKernelGGL((k_phase<ISLF_SPIN_BITPACK, false>), dim3(blocks), dim3(kBlock), 0, s, descs, st, work, n, phase);
-    }
+    if (kind == KIND_A)
+        hipLaunchKernelGGL((k_sweep<FMT, KIND_A>), dim3(grid), dim3(kBlock), 0, strm, descs, st, slabw, n_slab,
+                           mainw, reps, n_reps, s, flags);
+    else if (kind == KIND_B)
+        hipLaunchKernelGGL((k_sweep<FMT, KIND_B>), dim3(grid), dim3(kBlock), 0, strm, descs, st, slabw, n_slab,
+                           mainw, reps, n_reps, s, flags);
+    else
+        hipLaunchKernelGGL((k_sweep<FMT, KIND_F>), dim3(grid), dim3(kBlock), 0, strm, descs, st, slabw, n_slab,
+                           mainw, reps, n_reps, s, flags);
+}
+
+// kind 0 = A, 1 = B (grid n_slab + n_main), 2 = F (grid n_slab)
+hipError_t launch_sweep(int fmt, int kind, const RepDesc *descs, RepState *st, const Entry *slabw, long n_slab,
+                        const Entry *mainw, long n_main, const int *reps, int n_reps, uint32_t s, uint32_t flags,
+                        hipStream_t strm)
+{
+    const long g = kind == KIND_F ? n_slab : n_slab + n_main;
+    if (g <= 0) return hipSuccess;
+    if (fmt == ISLF_SPIN_INT8)
+        launch_sweep_fmt<ISLF_SPIN_INT8>(kind, (unsigned int)g, descs, st, slabw, n_slab, mainw, reps, n_reps, s,
+                                         flags, strm);
+    else
+        launch_sweep_fmt<ISLF_SPIN_BITPACK>(kind, (unsigned int)g, descs, st, slabw, n_slab, mainw, reps, n_reps,
+                                            s, flags, strm);
     return hipGetLastError();
 }
 
-hipError_t launch_end_sweep(const RepDesc *descs, RepState *st, const int *reps, int n, hipStream_t s)
+hipError_t launch_fold(const RepDesc *descs, RepState *st, const int *reps, int n_reps, uint32_t s,
+                       uint32_t advance, hipStream_t strm)
 {
-    if (n <= 0) return hipSuccess;
-    const int blocks = (n * 64 + kBlock - 1) / kBlock;
-    hipLaunchKernelGGL(k_end_sweep, dim3(blocks), dim3(kBlock), 0, s, descs, st, reps, n);
+    if (n_reps <= 0) return hipSuccess;
+    const int grid = (n_reps + kBlock / 64 - 1) / (kBlock / 64);
+    hipLaunchKernelGGL(k_fold, dim3(grid), dim3(kBlock), 0, strm, descs, st, reps, n_reps, s, advance);
     return hipGetLastError();
 }
 
@@ -1094,11 +1135,11 @@ const void *persistent_kernel(int fmt)
                                  : (const void *)k_persistent<ISLF_SPIN_BITPACK>;
 }
 
-hipError_t launch_persistent(int fmt, const RepDesc *descs, RepState *st, const Entry *wm, long nm,
-                             const Entry *ws, long ns, const int *reps, int nreps, uint32_t nsweeps,
+hipError_t launch_persistent(int fmt, const RepDesc *descs, RepState *st, const Entry *ws, long ns,
+                             const Entry *wm, long nm, const int *reps, int nreps, uint32_t nsweeps,
                              GridSync *sync, int grid, hipStream_t s)
 {
-    void *args[] = {(void *)&descs, (void *)&st, (void *)&wm, (void *)&nm, (void *)&ws, (void *)&ns,
+    void *args[] = {(void *)&descs, (void *)&st, (void *)&ws, (void *)&ns, (void *)&wm, (void *)&nm,
                     (void *)&reps, (void *)&nreps, (void *)&nsweeps, (void *)&sync};
     // fresh barrier counters for this launch (the error line is kept)
     hipLaunchKernelGGL(k_zero_u64, dim3(1), dim3(64), 0, s, (unsigned long long *)&sync->top, 16L);

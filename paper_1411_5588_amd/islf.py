@@ -296,7 +296,8 @@ class Context:
         _check(lib().islf_autotune(self._h, sweeps))
 
     def phase_timings(self, n_sweeps=4):
-        """Mean ms per launch and launch counts of (main phase, seam phase, end of sweep)."""
+        """Mean ms per launch and launch counts of (A, B, closing F + fold):
+        A = phase 3 of the previous sweep on row 0 + phase 0, B = phases 1 and 2."""
         ms = np.zeros(3, dtype=np.float64)
         cnt = np.zeros(3, dtype=np.uint32)
         _check(lib().islf_phase_timings(self._h, n_sweeps, ms.ctypes.data_as(C.c_void_p),

@@ -97,7 +97,7 @@ def test_phase_timings_are_real_sweeps():
         ms, cnt = ctx.phase_timings(3)
         ctx.sweep(2)
         recs = [ctx.measure(i, 0, 5) for i in range(len(ps))]
-    assert list(cnt) == [6, 6, 3]
+    assert list(cnt) == [3, 3, 1]
     assert (ms > 0).all()
     for i, p in enumerate(ps):
         _, o_rec, _ = oracle_trajectory(p, 5)
