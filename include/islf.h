@@ -234,6 +234,14 @@ islf_status islf_get_tile(const islf_ctx *ctx, int32_t rep, int32_t *tile);
 islf_status islf_set_tile(islf_ctx *ctx, int32_t rep, int32_t tile);
 islf_status islf_autotune(islf_ctx *ctx, uint32_t sweeps);
 
+/* Workgroups per A / B launch of the batched and plain forms; the work of a
+ * launch is split evenly over them.  0 (the default) means two per resident
+ * slot of the sweep kernels on the device; islf_get_grid reports the value in
+ * use.  Every choice computes the same result.  Changing it invalidates a
+ * captured graph.  Errors: EINVAL (NULL context, workgroups < 0 or > 2^20). */
+islf_status islf_set_grid(islf_ctx *ctx, int32_t workgroups);
+islf_status islf_get_grid(const islf_ctx *ctx, int32_t *workgroups);
+
 /* Runs n_sweeps sweeps of every live replica in the batched form (no graph)
  * with HIP events around each launch on the context's stream, and returns
  * the mean duration in milliseconds and the launch count of each kind:

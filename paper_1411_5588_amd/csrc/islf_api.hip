@@ -17,15 +17,15 @@
 #include "islf_internal.h"
 
 namespace islf {
-hipError_t launch_sweep(int fmt, int kind, const RepDesc *descs, RepState *st, const Entry *slabw, long n_slab,
-                        const Entry *mainw, long n_main, const int *reps, int n_reps, uint32_t s, uint32_t flags,
+hipError_t launch_sweep(int fmt, int kind, const RepDesc *descs, RepState *st, const Entry *items,
+                        const int *first, int grid, const int *reps, int n_reps, uint32_t s, uint32_t flags,
                         hipStream_t strm);
+hipError_t sweep_blocks_per_cu(int fmt, int *per_cu);
 hipError_t launch_fold(const RepDesc *descs, RepState *st, const int *reps, int n_reps, uint32_t s,
                        uint32_t advance, hipStream_t strm);
 const void *persistent_kernel(int fmt);
-hipError_t launch_persistent(int fmt, const RepDesc *descs, RepState *st, const Entry *ws, long ns,
-                             const Entry *wm, long nm, const int *reps, int nreps, uint32_t nsweeps,
-                             GridSync *sync, int grid, hipStream_t s);
+hipError_t launch_persistent(int fmt, const RepDesc *descs, RepState *st, const Entry *items, const int *first,
+                             const int *reps, int nreps, uint32_t nsweeps, GridSync *sync, int grid, hipStream_t s);
 hipError_t launch_init(int fmt, const RepDesc *descs, int rep, int mode, const int8_t *host, hipStream_t s);
 hipError_t launch_export(const RepDesc *descs, int rep, int8_t *out, hipStream_t s);
 hipError_t launch_recompute(const RepDesc *descs, int rep, const int8_t *spins, unsigned long long *out,
@@ -176,6 +176,17 @@ struct Replica {
     std::vector<Entry> main, slab;
 };
 
+// A launch plan: `grid` workgroups, workgroup b running items
+// [first[b], first[b+1]) (device arrays); slab items come first and sit in
+// workgroups [0, slab_grid).
+struct Plan {
+    Entry *items = nullptr;
+    int *first = nullptr;
+    long items_cap = 0, first_cap = 0;
+    int grid = 0, slab_grid = 0;
+    bool valid = false;
+};
+
 struct islf_ctx {
     int fmt = 0;
     uint32_t cap = 0;
@@ -185,7 +196,8 @@ struct islf_ctx {
     void *user = nullptr;
     int exec = ISLF_EXEC_BATCHED;
     int num_cu = 0;
-    int max_grid = 0;          // blocks of the phase kernels
+    int sweep_slots = 0;       // default workgroups per sweep launch (2 per resident slot)
+    int grid_override = 0;     // workgroups per batched / plain launch (0: sweep_slots)
     int persistent_grid = 0;   // co-resident blocks of the persistent kernel
 
     std::vector<Replica> reps;
@@ -196,10 +208,8 @@ struct islf_ctx {
     unsigned long long *d_scratch = nullptr;   // 64 x u64
     int *d_live = nullptr;                      // live replica ids
     int live_capacity = 0;
-    Entry *d_main = nullptr, *d_slab = nullptr;
-    long main_cap = 0, slab_cap = 0;
-    std::vector<long> main_off, main_len, slab_off, slab_len;  // per slot, within the device lists
-    long n_main = 0, n_slab = 0;
+    Plan batched, persistent;
+    std::vector<Plan> plain;                    // per slot
     std::vector<int> live;
     bool dirty = true;
 
@@ -307,7 +317,7 @@ static void build_work(Replica &R, int rep_id, int fmt)
     for (int x0 = 0; x0 < d.Lx; x0 += s.mx)
         for (int y0 = 2; y0 < d.Ly - 1; y0 += s.ty)
             for (int j0 = 0; j0 < J; j0 += s.tj)
-                R.main.push_back(Entry{rep_id, x0, y0, j0, std::min(s.mx, d.Lx - x0), 0, 0});
+                R.main.push_back(Entry{rep_id, x0, y0, j0, std::min(s.mx, d.Lx - x0), ITEM_MAIN});
     R.d.i8_tj = s.tj;
     R.d.i8_ty = s.ty;
     R.d.i8_mx = s.mx;
@@ -315,7 +325,7 @@ static void build_work(Replica &R, int rep_id, int fmt)
     const int P = (d.Lx + 1) / 2;
     for (int p0 = 0; p0 < P; p0 += sl.np)
         for (int j0 = 0; j0 < J; j0 += sl.nj)
-            R.slab.push_back(Entry{rep_id, p0, std::min(sl.np, P - p0), j0, std::min(sl.nj, J - j0), 0, 0});
+            R.slab.push_back(Entry{rep_id, p0, std::min(sl.np, P - p0), j0, std::min(sl.nj, J - j0), ITEM_SLAB});
 }
 
 static void fill_desc(Replica &R, int fmt, uint32_t cap)
@@ -373,63 +383,155 @@ static islf_status ensure_slots(islf_ctx *c, int n)
     return ISLF_OK;
 }
 
-// Rebuilds the concatenated work lists and the live list after a change of
-// membership or tiles.
+static void free_plan(islf_ctx *c, Plan &p)
+{
+    dev_free(c, p.items);
+    dev_free(c, p.first);
+    p = Plan();
+}
+
+// Splits the work into about `grid` runs of equal cost, one per workgroup:
+// workgroup b gets items [first[b], first[b+1]).  The slab items are spread
+// over the first min(grid, #slab) workgroups (so that a final launch of
+// those workgroups covers them all); main tiles follow in order and fill
+// every workgroup up to its share.  A main tile costs 4 units per x step and
+// may be cut between steps; a slab tile costs 6 units (1.5 steps) per task
+// per thread over its three row stages and is never cut.  Returns the number
+// of workgroups holding slab items.
+static int partition_items(const std::vector<Entry> &slab, const std::vector<Entry> &main, int grid,
+                           std::vector<Entry> &items, std::vector<int> &first)
+{
+    auto slab_cost = [](const Entry &e) -> long long {
+        const long long tasks = 6ll * e.y0 * e.nsteps;
+        return 6 * ((tasks + kBlock - 1) / kBlock);
+    };
+    const long long ns = (long long)slab.size();
+    long long W = 0, steps = 0;
+    for (const Entry &e : slab) W += slab_cost(e);
+    for (const Entry &e : main) steps += e.nsteps;
+    W += 4 * steps;
+    grid = (int)std::max(1ll, std::min((long long)grid, ns + steps));
+    const long long gs = std::min<long long>(grid, ns);   // workgroups holding slab items
+    items.clear();
+    first.assign(1, 0);
+    size_t mi = 0;   // next main tile and x offset inside it
+    int off = 0;
+    long long acc = 0;
+    for (int b = 0; b < grid; ++b) {
+        const long long target = (long long)((double)W * (b + 1) / grid);
+        if (b < gs)
+            for (long long k = b * ns / gs; k < (b + 1) * ns / gs; ++k) {
+                items.push_back(slab[k]);
+                acc += slab_cost(slab[k]);
+            }
+        while (mi < main.size() && (b == grid - 1 || target - acc >= 2)) {
+            const Entry &e = main[mi];
+            const int rem = e.nsteps - off;
+            const int take = b == grid - 1 ? rem : (int)std::min<long long>(rem, std::max(1ll, (target - acc + 2) / 4));
+            Entry piece = e;
+            piece.x0 = e.x0 + off;
+            piece.nsteps = take;
+            items.push_back(piece);
+            acc += 4ll * take;
+            off += take;
+            if (off == e.nsteps) {
+                ++mi;
+                off = 0;
+            }
+        }
+        first.push_back((int)items.size());
+        if (b + 1 >= gs && mi == main.size()) break;   // nothing left for later workgroups
+    }
+    return (int)gs;
+}
+
+static islf_status build_plan(islf_ctx *c, Plan &p, const std::vector<Entry> &slab, const std::vector<Entry> &main,
+                              int grid)
+{
+    std::vector<Entry> items;
+    std::vector<int> first;
+    p.slab_grid = partition_items(slab, main, grid, items, first);
+    p.grid = (int)first.size() - 1;
+    if ((long)items.size() > p.items_cap) {
+        dev_free(c, p.items);
+        p.items_cap = std::max<long>((long)items.size(), 2 * p.items_cap);
+        p.items = (Entry *)dev_alloc(c, sizeof(Entry) * p.items_cap);
+        if (!p.items) return fail(ISLF_ENOMEM, "cannot allocate a launch plan");
+    }
+    if ((long)first.size() > p.first_cap) {
+        dev_free(c, p.first);
+        p.first_cap = std::max<long>((long)first.size(), 2 * p.first_cap);
+        p.first = (int *)dev_alloc(c, sizeof(int) * p.first_cap);
+        if (!p.first) return fail(ISLF_ENOMEM, "cannot allocate a launch plan");
+    }
+    if (!items.empty())
+        HIP_TRY(hipMemcpyAsync(p.items, items.data(), sizeof(Entry) * items.size(), hipMemcpyHostToDevice, c->stream));
+    HIP_TRY(hipMemcpyAsync(p.first, first.data(), sizeof(int) * first.size(), hipMemcpyHostToDevice, c->stream));
+    HIP_TRY(hipStreamSynchronize(c->stream));
+    p.valid = true;
+    return ISLF_OK;
+}
+
+// Rebuilds the live list and the device descriptors after a change of
+// membership or tiles; launch plans are rebuilt on their next use.
 static islf_status sync_tables(islf_ctx *c)
 {
     if (!c->dirty) return ISLF_OK;
     c->live.clear();
-    std::vector<Entry> M, S;
     const int n = (int)c->reps.size();
-    c->main_off.assign(n, 0); c->main_len.assign(n, 0);
-    c->slab_off.assign(n, 0); c->slab_len.assign(n, 0);
-    for (int i = 0; i < n; ++i) {
-        Replica &R = c->reps[i];
-        if (!R.live) continue;
-        c->live.push_back(i);
-        c->main_off[i] = (long)M.size();
-        c->main_len[i] = (long)R.main.size();
-        M.insert(M.end(), R.main.begin(), R.main.end());
-        c->slab_off[i] = (long)S.size();
-        c->slab_len[i] = (long)R.slab.size();
-        S.insert(S.end(), R.slab.begin(), R.slab.end());
-    }
-    long long slot = 0;
-    for (Entry &e : M) {
-        e.slot0 = slot;
-        slot += e.nsteps;
-    }
-    if ((long)M.size() > c->main_cap) {
-        dev_free(c, c->d_main);
-        c->main_cap = std::max<long>((long)M.size(), 2 * c->main_cap);
-        c->d_main = (Entry *)dev_alloc(c, sizeof(Entry) * c->main_cap);
-        if (!c->d_main) return fail(ISLF_ENOMEM, "cannot allocate work list");
-    }
-    if ((long)S.size() > c->slab_cap) {
-        dev_free(c, c->d_slab);
-        c->slab_cap = std::max<long>((long)S.size(), 2 * c->slab_cap);
-        c->d_slab = (Entry *)dev_alloc(c, sizeof(Entry) * c->slab_cap);
-        if (!c->d_slab) return fail(ISLF_ENOMEM, "cannot allocate work list");
-    }
+    for (int i = 0; i < n; ++i)
+        if (c->reps[i].live) c->live.push_back(i);
     if ((int)c->live.size() > c->live_capacity) {
         dev_free(c, c->d_live);
         c->live_capacity = std::max<int>((int)c->live.size(), 2 * c->live_capacity);
         c->d_live = (int *)dev_alloc(c, sizeof(int) * c->live_capacity);
         if (!c->d_live) return fail(ISLF_ENOMEM, "cannot allocate live list");
     }
-    if (!M.empty()) HIP_TRY(hipMemcpyAsync(c->d_main, M.data(), sizeof(Entry) * M.size(), hipMemcpyHostToDevice, c->stream));
-    if (!S.empty()) HIP_TRY(hipMemcpyAsync(c->d_slab, S.data(), sizeof(Entry) * S.size(), hipMemcpyHostToDevice, c->stream));
     if (!c->live.empty())
         HIP_TRY(hipMemcpyAsync(c->d_live, c->live.data(), sizeof(int) * c->live.size(), hipMemcpyHostToDevice, c->stream));
-    for (int i = 0; i < n; ++i) {
-        if (!c->reps[i].live) continue;
+    for (int i : c->live)
         HIP_TRY(hipMemcpyAsync(c->d_desc + i, &c->reps[i].d, sizeof(RepDesc), hipMemcpyHostToDevice, c->stream));
-    }
     HIP_TRY(hipStreamSynchronize(c->stream));
-    c->n_main = (long)M.size();
-    c->n_slab = (long)S.size();
+    c->batched.valid = false;
+    c->persistent.valid = false;
+    for (Plan &p : c->plain) p.valid = false;
     c->dirty = false;
     c->graph_valid = false;
+    return ISLF_OK;
+}
+
+// The plans the context's execution form launches, built if needed.
+static islf_status prepare_plans(islf_ctx *c, int exec)
+{
+    islf_status st = sync_tables(c);
+    if (st != ISLF_OK) return st;
+    auto lists = [&](const std::vector<int> &reps, std::vector<Entry> &S, std::vector<Entry> &M) {
+        for (int r : reps) {
+            S.insert(S.end(), c->reps[r].slab.begin(), c->reps[r].slab.end());
+            M.insert(M.end(), c->reps[r].main.begin(), c->reps[r].main.end());
+        }
+    };
+    if (c->live.empty()) return ISLF_OK;
+    if (exec == ISLF_EXEC_BATCHED && !c->batched.valid) {
+        std::vector<Entry> S, M;
+        lists(c->live, S, M);
+        return build_plan(c, c->batched, S, M, c->grid_override ? c->grid_override : c->sweep_slots);
+    }
+    if (exec == ISLF_EXEC_PERSISTENT && !c->persistent.valid) {
+        std::vector<Entry> S, M;
+        lists(c->live, S, M);
+        return build_plan(c, c->persistent, S, M, c->persistent_grid);
+    }
+    if (exec == ISLF_EXEC_PLAIN) {
+        if (c->plain.size() < c->reps.size()) c->plain.resize(c->reps.size());
+        for (int r : c->live) {
+            if (c->plain[r].valid) continue;
+            std::vector<Entry> S, M;
+            lists(std::vector<int>(1, r), S, M);
+            st = build_plan(c, c->plain[r], S, M, c->grid_override ? c->grid_override : c->sweep_slots);
+            if (st != ISLF_OK) return st;
+        }
+    }
     return ISLF_OK;
 }
 
@@ -505,8 +607,9 @@ static void destroy_ctx(islf_ctx *c)
     dev_free(c, c->d_sync);
     dev_free(c, c->d_scratch);
     dev_free(c, c->d_live);
-    dev_free(c, c->d_main);
-    dev_free(c, c->d_slab);
+    free_plan(c, c->batched);
+    free_plan(c, c->persistent);
+    for (Plan &p : c->plain) free_plan(c, p);
     delete c;
 }
 
@@ -543,7 +646,11 @@ extern "C" islf_status islf_create_with_allocator(const islf_replica_desc *reps,
         return fail(ISLF_EDEVICE, "no HIP device");
     }
     c->num_cu = prop.multiProcessorCount;
-    c->max_grid = c->num_cu * 8;
+    int per_cu_sweep = 0;
+    if (sweep_blocks_per_cu(spin_format, &per_cu_sweep) != hipSuccess || per_cu_sweep < 1) per_cu_sweep = 1;
+    // two workgroups per resident slot: measured faster than one (a single
+    // round leaves slots idle while the last workgroups finish)
+    c->sweep_slots = 2 * c->num_cu * per_cu_sweep;
     int per_cu = 0;
     if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, persistent_kernel(spin_format), kBlock, 0) != hipSuccess ||
         per_cu < 1)
@@ -666,12 +773,12 @@ extern "C" islf_status islf_set_exec(islf_ctx *ctx, int32_t mode)
     return ISLF_OK;
 }
 
-// Enqueues n >= 1 sweeps of the replicas in the device list dl (nl ids) in
-// the batched form, over the given slab and main lists: A(s) B(s) for each
-// sweep, then F and the closing fold.  Optional events bracket each launch
-// (A and B of sweep s at ev[4s..4s+3], F + fold at ev[4n], ev[4n+1]).
-static hipError_t enqueue_batched(islf_ctx *c, const Entry *ws, long ns, const Entry *wm, long nm, const int *dl,
-                                  int nl, uint32_t n, hipEvent_t *ev = nullptr)
+// Enqueues n >= 1 sweeps of the replicas in the device list dl (nl ids) over
+// a plan: A(s) B(s) for each sweep, then F and the closing fold.  Optional
+// events bracket each launch (A and B of sweep s at ev[4s..4s+3], F + fold
+// at ev[4n], ev[4n+1]).
+static hipError_t enqueue_plan(islf_ctx *c, const Plan &p, const int *dl, int nl, uint32_t n,
+                               hipEvent_t *ev = nullptr)
 {
     hipError_t e = hipSuccess;
     auto mark = [&](size_t i) {
@@ -680,51 +787,53 @@ static hipError_t enqueue_batched(islf_ctx *c, const Entry *ws, long ns, const E
     for (uint32_t s = 0; s < n && e == hipSuccess; ++s) {
         mark(4 * (size_t)s);
         if (e == hipSuccess)
-            e = launch_sweep(c->fmt, KIND_A, c->d_desc, c->d_state, ws, ns, wm, nm, dl, nl, s, s ? FLAG_PREV : 0u,
-                             c->stream);
+            e = launch_sweep(c->fmt, KIND_A, c->d_desc, c->d_state, p.items, p.first, p.grid, dl, nl, s,
+                             s ? FLAG_PREV : 0u, c->stream);
         mark(4 * (size_t)s + 1);
         mark(4 * (size_t)s + 2);
         if (e == hipSuccess)
-            e = launch_sweep(c->fmt, KIND_B, c->d_desc, c->d_state, ws, ns, wm, nm, dl, nl, s, s ? FLAG_FOLD : 0u,
-                             c->stream);
+            e = launch_sweep(c->fmt, KIND_B, c->d_desc, c->d_state, p.items, p.first, p.grid, dl, nl, s,
+                             s ? FLAG_FOLD : 0u, c->stream);
         mark(4 * (size_t)s + 3);
     }
     mark(4 * (size_t)n);
     if (e == hipSuccess)
-        e = launch_sweep(c->fmt, KIND_F, c->d_desc, c->d_state, ws, ns, wm, nm, dl, nl, n - 1, 0u, c->stream);
+        e = launch_sweep(c->fmt, KIND_F, c->d_desc, c->d_state, p.items, p.first, p.slab_grid, dl, nl, n - 1, 0u,
+                         c->stream);
     if (e == hipSuccess) e = launch_fold(c->d_desc, c->d_state, dl, nl, n - 1, n, c->stream);
     mark(4 * (size_t)n + 1);
     return e;
 }
 
-// Enqueues n sweeps in the context's execution form (no checks, no sync).
+// Enqueues n sweeps in the context's execution form (plans prepared, no
+// checks, no sync).
 static islf_status enqueue_sweeps(islf_ctx *c, uint32_t n)
 {
     const int nl = (int)c->live.size();
     if (nl == 0 || n == 0) return ISLF_OK;
     if (c->exec == ISLF_EXEC_PERSISTENT) {
-        hipError_t e = launch_persistent(c->fmt, c->d_desc, c->d_state, c->d_slab, c->n_slab, c->d_main, c->n_main,
-                                         c->d_live, nl, n, c->d_sync, c->persistent_grid, c->stream);
+        const Plan &p = c->persistent;
+        hipError_t e = launch_persistent(c->fmt, c->d_desc, c->d_state, p.items, p.first, c->d_live, nl, n,
+                                         c->d_sync, p.grid, c->stream);
         if (e != hipSuccess) return fail(ISLF_EDEVICE, "persistent launch failed: %s", hipGetErrorString(e));
         return ISLF_OK;
     }
     if (c->exec == ISLF_EXEC_BATCHED) {
-        HIP_TRY(enqueue_batched(c, c->d_slab, c->n_slab, c->d_main, c->n_main, c->d_live, nl, n));
+        HIP_TRY(enqueue_plan(c, c->batched, c->d_live, nl, n));
         return ISLF_OK;
     }
     // plain: one lattice per launch; replica r's fold list is its entry in d_live
     for (uint32_t s = 0; s < n; ++s)
         for (int k = 0; k < 2; ++k)
             for (int li = 0; li < nl; ++li) {
-                const int r = c->live[li];
-                HIP_TRY(launch_sweep(c->fmt, k, c->d_desc, c->d_state, c->d_slab + c->slab_off[r], c->slab_len[r],
-                                     c->d_main + c->main_off[r], c->main_len[r], c->d_live + li, 1, s,
-                                     s ? (k == 0 ? FLAG_PREV : FLAG_FOLD) : 0u, c->stream));
+                const Plan &p = c->plain[c->live[li]];
+                HIP_TRY(launch_sweep(c->fmt, k, c->d_desc, c->d_state, p.items, p.first, p.grid, c->d_live + li, 1,
+                                     s, s ? (k == 0 ? FLAG_PREV : FLAG_FOLD) : 0u, c->stream));
             }
     for (int li = 0; li < nl; ++li) {
-        const int r = c->live[li];
-        HIP_TRY(launch_sweep(c->fmt, KIND_F, c->d_desc, c->d_state, c->d_slab + c->slab_off[r], c->slab_len[r],
-                             c->d_main + c->main_off[r], c->main_len[r], c->d_live + li, 1, n - 1, 0u, c->stream));
+        const Plan &p = c->plain[c->live[li]];
+        HIP_TRY(launch_sweep(c->fmt, KIND_F, c->d_desc, c->d_state, p.items, p.first, p.slab_grid, c->d_live + li,
+                             1, n - 1, 0u, c->stream));
     }
     HIP_TRY(launch_fold(c->d_desc, c->d_state, c->d_live, nl, n - 1, n, c->stream));
     return ISLF_OK;
@@ -741,7 +850,7 @@ static islf_status check_sweep_range(islf_ctx *c, uint64_t n)
 extern "C" islf_status islf_sweep(islf_ctx *ctx, uint32_t n_sweeps)
 {
     if (!ctx) return fail(ISLF_EINVAL, "NULL context");
-    islf_status st = sync_tables(ctx);
+    islf_status st = prepare_plans(ctx, ctx->exec);
     if (st != ISLF_OK) return st;
     st = check_sweep_range(ctx, n_sweeps);
     if (st != ISLF_OK) return st;
@@ -938,7 +1047,7 @@ extern "C" islf_status islf_graph_capture(islf_ctx *ctx, uint32_t k_sweeps)
     if (!ctx) return fail(ISLF_EINVAL, "NULL context");
     if (k_sweeps < 1) return fail(ISLF_EINVAL, "k_sweeps must be >= 1");
     if (!ctx->stream) return fail(ISLF_ESTATE, "graph capture needs a non-default stream");
-    islf_status st = sync_tables(ctx);
+    islf_status st = prepare_plans(ctx, ctx->exec);
     if (st != ISLF_OK) return st;
     if (ctx->graph_exec) {
         (void)hipGraphExecDestroy(ctx->graph_exec);
@@ -1007,9 +1116,9 @@ extern "C" islf_status islf_set_tile(islf_ctx *ctx, int32_t rep, int32_t tile)
 }
 
 // Times one tile variant for one size class: the class's replicas sweep
-// `sweeps` times through kernels launched on their own work lists (events on
-// the context stream).  Spins, records and state are restored afterwards by
-// the caller.
+// `sweeps` times in the batched form over a plan of their own (events on the
+// context stream).  Spins, records and state are restored afterwards by the
+// caller.
 static islf_status time_variant(islf_ctx *c, const std::vector<int> &cls, int tile, uint32_t sweeps, double *ms)
 {
     std::vector<Entry> M, S;
@@ -1021,32 +1130,29 @@ static islf_status time_variant(islf_ctx *c, const std::vector<int> &cls, int ti
         S.insert(S.end(), R.slab.begin(), R.slab.end());
         HIP_TRY(hipMemcpyAsync(c->d_desc + r, &R.d, sizeof(RepDesc), hipMemcpyHostToDevice, c->stream));
     }
-    long long slot = 0;
-    for (Entry &e : M) { e.slot0 = slot; slot += e.nsteps; }
-    Entry *dm = (Entry *)dev_alloc(c, sizeof(Entry) * std::max<size_t>(1, M.size()));
-    Entry *ds = (Entry *)dev_alloc(c, sizeof(Entry) * S.size());
+    Plan plan;
+    islf_status st = build_plan(c, plan, S, M, c->grid_override ? c->grid_override : c->sweep_slots);
+    if (st != ISLF_OK) {
+        free_plan(c, plan);
+        return st;
+    }
     int *dl = (int *)dev_alloc(c, sizeof(int) * cls.size());
     hipEvent_t e0 = nullptr, e1 = nullptr;
-    hipError_t err = (dm && ds && dl) ? hipSuccess : hipErrorOutOfMemory;
+    hipError_t err = dl ? hipSuccess : hipErrorOutOfMemory;
     if (err == hipSuccess) err = hipEventCreate(&e0);
     if (err == hipSuccess) err = hipEventCreate(&e1);
-    if (err == hipSuccess && !M.empty())
-        err = hipMemcpyAsync(dm, M.data(), sizeof(Entry) * M.size(), hipMemcpyHostToDevice, c->stream);
-    if (err == hipSuccess) err = hipMemcpyAsync(ds, S.data(), sizeof(Entry) * S.size(), hipMemcpyHostToDevice, c->stream);
     if (err == hipSuccess) err = hipMemcpyAsync(dl, cls.data(), sizeof(int) * cls.size(), hipMemcpyHostToDevice, c->stream);
     // one warm-up sweep, then the timed run
-    if (err == hipSuccess) err = enqueue_batched(c, ds, (long)S.size(), dm, (long)M.size(), dl, (int)cls.size(), 1);
+    if (err == hipSuccess) err = enqueue_plan(c, plan, dl, (int)cls.size(), 1);
     if (err == hipSuccess) err = hipEventRecord(e0, c->stream);
-    if (err == hipSuccess)
-        err = enqueue_batched(c, ds, (long)S.size(), dm, (long)M.size(), dl, (int)cls.size(), sweeps);
+    if (err == hipSuccess) err = enqueue_plan(c, plan, dl, (int)cls.size(), sweeps);
     if (err == hipSuccess) err = hipEventRecord(e1, c->stream);
     if (err == hipSuccess) err = hipStreamSynchronize(c->stream);
     float t = 0.f;
     if (err == hipSuccess) err = hipEventElapsedTime(&t, e0, e1);
     if (e0) (void)hipEventDestroy(e0);
     if (e1) (void)hipEventDestroy(e1);
-    dev_free(c, dm);
-    dev_free(c, ds);
+    free_plan(c, plan);
     dev_free(c, dl);
     if (err != hipSuccess) return fail(ISLF_EDEVICE, "autotune trial failed: %s", hipGetErrorString(err));
     *ms = t;
@@ -1130,11 +1236,29 @@ extern "C" islf_status islf_autotune(islf_ctx *ctx, uint32_t sweeps)
     return sync_tables(ctx);
 }
 
+extern "C" islf_status islf_set_grid(islf_ctx *ctx, int32_t workgroups)
+{
+    if (!ctx) return fail(ISLF_EINVAL, "NULL context");
+    if (workgroups < 0 || workgroups > (1 << 20)) return fail(ISLF_EINVAL, "invalid workgroup count %d", workgroups);
+    ctx->grid_override = workgroups;
+    ctx->batched.valid = false;
+    for (Plan &p : ctx->plain) p.valid = false;
+    ctx->graph_valid = false;
+    return ISLF_OK;
+}
+
+extern "C" islf_status islf_get_grid(const islf_ctx *ctx, int32_t *workgroups)
+{
+    if (!ctx || !workgroups) return fail(ISLF_EINVAL, "NULL argument");
+    *workgroups = ctx->grid_override ? ctx->grid_override : ctx->sweep_slots;
+    return ISLF_OK;
+}
+
 extern "C" islf_status islf_phase_timings(islf_ctx *ctx, uint32_t n_sweeps, double *mean_ms, uint32_t *launches)
 {
     if (!ctx || !mean_ms || !launches) return fail(ISLF_EINVAL, "NULL argument");
     if (n_sweeps < 1) return fail(ISLF_EINVAL, "n_sweeps must be >= 1");
-    islf_status st = sync_tables(ctx);
+    islf_status st = prepare_plans(ctx, ISLF_EXEC_BATCHED);
     if (st != ISLF_OK) return st;
     st = check_sweep_range(ctx, n_sweeps);
     if (st != ISLF_OK) return st;
@@ -1146,9 +1270,7 @@ extern "C" islf_status islf_phase_timings(islf_ctx *ctx, uint32_t n_sweeps, doub
                 if (f) (void)hipEventDestroy(f);
             return fail(ISLF_EDEVICE, "cannot create events");
         }
-    hipError_t err = nl ? enqueue_batched(ctx, ctx->d_slab, ctx->n_slab, ctx->d_main, ctx->n_main, ctx->d_live, nl,
-                                          n_sweeps, ev.data())
-                        : hipSuccess;
+    hipError_t err = nl ? enqueue_plan(ctx, ctx->batched, ctx->d_live, nl, n_sweeps, ev.data()) : hipSuccess;
     if (err == hipSuccess) err = hipStreamSynchronize(ctx->stream);
     double sum[3] = {0, 0, 0};
     uint32_t cnt[3] = {0, 0, 0};

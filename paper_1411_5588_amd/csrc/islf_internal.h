@@ -17,19 +17,18 @@ constexpr int kThrEntries = kClasses * kThrPerClass;
 constexpr int kPadEntry = kThrEntries - 1;   // class 3, u = 1, cnt = 7: never a real site
 constexpr int kMaxMarch = 256;       // x planes one thread may march through per entry
 
-// One tile of work for one replica.  j counts 8-byte chunks (int8 format) or
+// One item of work for one replica.  j counts 8-byte chunks (int8 format) or
 // 32-bit words of one sublattice row (bit-packed).
-// Main tile (rows 2 .. Ly-2): a box of rows/columns starting at (x0, y0, j0)
-// whose extent is the replica's tile shape, marched through nsteps x planes
-// from x0; the entries of a main list number their steps consecutively from
-// slot0, so that a fixed grid can split a list evenly at step granularity.
-// Seam-slab tile (rows Ly-1, 0, 1): x0 = first x pair p (planes p and
+// Main tile (kind 0, rows 2 .. Ly-2): a box of rows/columns starting at
+// (x0, y0, j0) whose extent is the replica's tile shape, marched through
+// nsteps x planes from x0 (a launch plan may cut a tile into pieces along x).
+// Seam-slab tile (kind 1, rows Ly-1, 0, 1): x0 = first x pair p (planes p and
 // Lx-1-p), y0 = number of consecutive pairs, j0 = first column,
 // nsteps = number of columns.
+enum { ITEM_MAIN = 0, ITEM_SLAB = 1 };
 struct Entry {
     int32_t rep, x0, y0, j0;
-    int32_t nsteps, pad_;
-    long long slot0;
+    int32_t nsteps, kind;
 };
 
 // Launch kinds of a run of sweeps and their flags.

@@ -104,8 +104,12 @@ struct TD {
 struct Tables {
     uint64_t thr[kThrEntries];
     TD td[kThrEntries];
+    // bulk class, two sites at once: entry (e1 << 4) | e0 holds the thr - 1
+    // of table indices e0 and e1 (bit-packed main tiles)
+    uint2 pair[256];
 };
 
+template <bool PAIRS = false>
 __device__ __forceinline__ void load_tables(const RepDesc &d, Tables *t)
 {
     for (int k = threadIdx.x; k < kThrEntries; k += blockDim.x) {
@@ -113,6 +117,8 @@ __device__ __forceinline__ void load_tables(const RepDesc &d, Tables *t)
         t->td[k].thr_m1 = d.thr_m1[k];
         t->td[k].dpack = d.dpack[k];
     }
+    if (PAIRS)
+        for (int k = threadIdx.x; k < 256; k += blockDim.x) t->pair[k] = make_uint2(d.thr_m1[k & 15], d.thr_m1[k >> 4]);
 }
 
 // Per-replica parameters as the update loop uses them: loaded once per
@@ -476,9 +482,129 @@ __device__ __forceinline__ uint32_t spread_nibbles(uint32_t x)
 
 // bit-packed format, main tiles (rows 2 .. Ly-2): a thread owns word w of its
 // row's sublattices and marches through the x planes; at plane x it updates
-// the sublattice of the phase's parity (it alternates with x).  Neighbour
-// counts are bit-sliced; the 4-bit table index 8u + cnt of every site is
-// gathered into nibbles, eight sites per word.
+// the sublattice of the phase's parity q (q alternates with x).  Of the words
+// a step reads, the other sublattice of plane x (O) and the same sublattice
+// of plane x+1 (xp) are the next step's x-1 and other-sublattice words, so
+// they stay in registers; the rest (own word, z-edge word, y neighbours,
+// plane x+2) are loaded one step ahead.  None of these words is written in
+// this phase.  Neighbour counts are bit-sliced; the 4-bit table index
+// 8u + cnt of every site is gathered into nibbles, eight sites per word.
+struct BpStep {
+    uint32_t S, A, yp, ym, xp;
+};
+
+__device__ __forceinline__ BpStep bp_load_step(const gcu8 *base, uint32_t own, uint32_t edge, uint32_t RWB,
+                                               uint32_t XB, bool has_xp)
+{
+    BpStep n;
+    n.S = *(gcu32 *)(base + own);
+    n.A = *(gcu32 *)(base + edge);
+    n.yp = *(gcu32 *)(base + own + RWB);
+    n.ym = *(gcu32 *)(base + own - RWB);
+    n.xp = has_xp ? *(gcu32 *)(base + own + XB) : 0u;
+    return n;
+}
+
+// 8 x 8 bit-matrix transpose of the 64-bit value (hi:lo): bit c of byte r
+// moves to bit r of byte c (three delta swaps).
+__device__ __forceinline__ void transpose8x8(uint32_t &lo, uint32_t &hi)
+{
+    uint64_t x = ((uint64_t)hi << 32) | lo, t;
+    t = (x ^ (x >> 7)) & 0x00AA00AA00AA00AAull;
+    x = x ^ t ^ (t << 7);
+    t = (x ^ (x >> 14)) & 0x0000CCCC0000CCCCull;
+    x = x ^ t ^ (t << 14);
+    t = (x ^ (x >> 28)) & 0x00000000F0F0F0F0ull;
+    x = x ^ t ^ (t << 28);
+    lo = (uint32_t)x;
+    hi = (uint32_t)(x >> 32);
+}
+
+// Accept bits of the 32 sites of one word, bulk class, thresholds read from
+// the pair table for the site pairs (j, j+16).  The pair indices come from
+// the bit planes (b0, b1, b2, S) by byte permutes and two 8 x 8 transposes:
+// byte l of w[g] is (e(4g+l+16) << 4) | e(4g+l), e = 8u + cnt.  Philox call
+// c (counter gq + 2c) draws for sites 4c .. 4c+3.
+__device__ __forceinline__ uint32_t bp_flips_pairs(uint32_t S, uint32_t b2, uint32_t b1, uint32_t b0, uint32_t gq,
+                                                   const RepView &v, const Tables *tb)
+{
+    // rows of the two 8 x 8 blocks: bytes {b0, b1, b2, S} of sites 8k..8k+7
+    // (low word) and 8k+16..8k+23 (high word), block k = 0, 1
+    uint32_t A = __builtin_amdgcn_perm(b1, b0, 0x06020400u);
+    uint32_t B = __builtin_amdgcn_perm(S, b2, 0x06020400u);
+    uint32_t w[4];
+    w[0] = __builtin_amdgcn_perm(B, A, 0x05040100u);
+    w[1] = __builtin_amdgcn_perm(B, A, 0x07060302u);
+    A = __builtin_amdgcn_perm(b1, b0, 0x07030501u);
+    B = __builtin_amdgcn_perm(S, b2, 0x07030501u);
+    w[2] = __builtin_amdgcn_perm(B, A, 0x05040100u);
+    w[3] = __builtin_amdgcn_perm(B, A, 0x07060302u);
+    transpose8x8(w[0], w[1]);
+    transpose8x8(w[2], w[3]);
+    uint32_t F = 0;
+    // not unrolled (keeps two draws live at a time); w[0] always holds the
+    // current iteration's pair indices
+#pragma unroll 1
+    for (int g = 0; g < 4; ++g) {
+        uint32_t r0[4], r1[4];
+        philox10(gq + 2u * (uint32_t)g, v.t, v.replica, 0u, v.key0, v.key1, r0);
+        philox10(gq + 2u * (uint32_t)(g + 4), v.t, v.replica, 0u, v.key0, v.key1, r1);
+        uint32_t Fg = 0;
+#pragma unroll
+        for (int l = 0; l < 4; ++l) {
+            const uint2 t = tb->pair[(w[0] >> (8 * l)) & 0xFFu];
+            Fg |= (r0[l] <= t.x ? 1u : 0u) << l;
+            Fg |= (r1[l] <= t.y ? 1u : 0u) << (l + 16);
+        }
+        F |= Fg << (4 * g);
+        w[0] = w[1];
+        w[1] = w[2];
+        w[2] = w[3];
+    }
+    return F;
+}
+
+// Accept bits of the 32 sites of one word, any class: eight Philox draws
+// (counters gq + 2i, i = 0..7, four sites each); the 4-bit table index
+// 8u + cnt of every site is gathered into nibbles (eight sites per word) and
+// looked up one site at a time (64-bit compare under NEVER).
+template <bool NEVER>
+__device__ __forceinline__ uint32_t bp_flips(uint32_t S, uint32_t b2, uint32_t b1, uint32_t b0, uint32_t gq,
+                                             const RepView &v, const Tables *tb, int cls)
+{
+    const TD *tdc = tb->td + cls * kThrPerClass;
+    const uint64_t *thc = tb->thr + cls * kThrPerClass;
+    uint32_t F = 0;
+    // one byte of sites per iteration, not unrolled: unrolling lets the
+    // compiler keep all 32 draws live and costs occupancy
+#pragma unroll 1
+    for (int h = 0; h < 4; ++h) {
+        // eight sites 8h .. 8h+7: nibble i holds 8u + cnt of site 8h+i
+        const int sh = 8 * h;
+        const uint32_t nib = (spread_nibbles(S >> sh) << 3) | (spread_nibbles(b2 >> sh) << 2) |
+                             (spread_nibbles(b1 >> sh) << 1) | spread_nibbles(b0 >> sh);
+        uint32_t Fh = 0;
+#pragma unroll
+        for (int g2 = 0; g2 < 2; ++g2) {
+            uint32_t rnd[4];
+            philox10(gq + 2u * (uint32_t)(2 * h + g2), v.t, v.replica, 0u, v.key0, v.key1, rnd);
+            {
+#pragma unroll
+                for (int l = 0; l < 4; ++l) {
+                    const int i = 4 * g2 + l;
+                    const uint32_t e = (nib >> (4 * i)) & 0xFu;
+                    bool acc;
+                    if (NEVER) acc = (uint64_t)rnd[l] < thc[e];
+                    else acc = rnd[l] <= tdc[e].thr_m1;
+                    Fh |= (uint32_t)acc << i;
+                }
+            }
+        }
+        F |= Fh << sh;
+    }
+    return F;
+}
+
 template <bool NEVER>
 __device__ __forceinline__ void bp_march(const RepView &v, const Entry &en, int k_lo, int k_hi, int parity,
                                          const Tables *tb, Acc &a)
@@ -491,42 +617,45 @@ __device__ __forceinline__ void bp_march(const RepView &v, const Entry &en, int 
     if (ty >= v.ty || y >= v.Ly - 1 || w >= v.Wq) return;   // main rows are 2 .. Ly-2
     const int Lx = v.Lx, Ly = v.Ly, C = v.C, Wq = v.Wq;
     const int nbits = v.Lz >> 1;
-    const uint32_t RW = 2u * (uint32_t)Wq;
-    const uint32_t xstride = (uint32_t)Ly * RW;
-    const uint32_t *words = (const uint32_t *)v.spins;
+    const uint32_t SB = 4u * (uint32_t)Wq;    // bytes of one sublattice row
+    const uint32_t RWB = 2u * SB;             // bytes of one row
+    const uint32_t XB = (uint32_t)Ly * RWB;   // bytes of one x plane
+    const gcu8 *base = (const gcu8 *)v.spins;
     gu32 *wout = (gu32 *)v.spins;
     const int nb_here = min(32, nbits - 32 * w);
     const uint32_t vmask = nb_here >= 32 ? 0xFFFFFFFFu : ((1u << nb_here) - 1u);
-    const int wl = (nbits - 1) >> 5, bl = (nbits - 1) & 31;   // last bit of a sublattice row
+    // z edges: an even-z word (q = 0) needs bit 31 of odd word w-1 (the last
+    // odd bit when w = 0); an odd-z word (q = 1) needs bit 0 of even word w+1
+    // (of word 0 for the last word, placed at bit nb_here-1)
+    const bool lastw = (w == Wq - 1);
+    const uint32_t e0 = 4u * (uint32_t)(w > 0 ? w - 1 : (nbits - 1) >> 5);
+    const uint32_t e1 = 4u * (uint32_t)(lastw ? 0 : w + 1);
+    const uint32_t csh0 = w > 0 ? 31u : (uint32_t)((nbits - 1) & 31);
+    const uint32_t zsh1 = lastw ? (uint32_t)(nb_here - 1) : 31u;
     const int x0 = en.x0 + k_lo;
     const int x1 = min(en.x0 + k_hi, Lx);
+    int q = (parity + x0 + y) & 1;
+    // byte offset of row (x, y), word w of sublattice 0
+    uint32_t rw = ((uint32_t)x0 * (uint32_t)Ly + (uint32_t)y) * RWB + 4u * (uint32_t)w;
+    const uint32_t gstep = 2u * (uint32_t)Ly * (uint32_t)C;
+    uint32_t gq = ((((uint32_t)x0 * (uint32_t)Ly + (uint32_t)y) * (uint32_t)C + 8u * (uint32_t)w) << 1) |
+                  (uint32_t)q;
+
+    auto own_of = [&](uint32_t r, int qq) { return r + (qq ? SB : 0u); };
+    auto edge_of = [&](uint32_t r, int qq) { return r - 4u * (uint32_t)w + (qq ? e1 : SB + e0); };
+    uint32_t O = *(gcu32 *)(base + own_of(rw, q ^ 1));
+    uint32_t xm = (x0 > 0) ? *(gcu32 *)(base + own_of(rw, q) - XB) : 0u;
+    BpStep cur = bp_load_step(base, own_of(rw, q), edge_of(rw, q), RWB, XB, x0 < Lx - 1);
     int dB = 0, dM = 0;
     for (int x = x0; x < x1; ++x) {
-        const uint32_t row = (uint32_t)x * (uint32_t)Ly + (uint32_t)y;
-        const int q = (parity + x + y) & 1;
-        const uint32_t rb = row * RW;
-        const uint32_t own = rb + (uint32_t)(q * Wq + w);
-        const uint32_t othb = rb + (uint32_t)((q ^ 1) * Wq);
-        const uint32_t S = *(gcu32 *)(words + own);
-        const uint32_t O = *(gcu32 *)(words + othb + w);
-        uint32_t zm, zp;
-        if (q == 0) {
-            // z = 2i: z+1 is odd index i, z-1 is odd index i-1 (wrapping)
-            const uint32_t src = (w > 0) ? *(gcu32 *)(words + othb + w - 1) : *(gcu32 *)(words + othb + wl);
-            const uint32_t carry = (w > 0) ? (src >> 31) : ((src >> bl) & 1u);
-            zp = O;
-            zm = (O << 1) | carry;
-        } else {
-            // z = 2i+1: z-1 is even index i, z+1 is even index i+1 (wrapping)
-            const bool lastw = (w == Wq - 1);
-            const uint32_t inb = *(gcu32 *)(words + othb + (lastw ? 0 : w + 1)) & 1u;
-            zm = O;
-            zp = (O >> 1) | (inb << (lastw ? (nb_here - 1) : 31));
-        }
-        const uint32_t yp = *(gcu32 *)(words + own + RW);
-        const uint32_t ym = *(gcu32 *)(words + own - RW);
-        const uint32_t xm = (x > 0) ? *(gcu32 *)(words + own - xstride) : 0u;
-        const uint32_t xp = (x < Lx - 1) ? *(gcu32 *)(words + own + xstride) : 0u;
+        const uint32_t own = own_of(rw, q);
+        BpStep nxt;
+        const bool more = x + 1 < x1;
+        if (more) nxt = bp_load_step(base, own_of(rw + XB, q ^ 1), edge_of(rw + XB, q ^ 1), RWB, XB, x + 2 < Lx);
+        const uint32_t S = cur.S;
+        const uint32_t zm = q ? O : ((O << 1) | ((cur.A >> csh0) & 1u));
+        const uint32_t zp = q ? ((O >> 1) | ((cur.A & 1u) << zsh1)) : O;
+        const uint32_t ym = cur.ym, yp = cur.yp, xp = cur.xp;
 
         const uint32_t s1 = zm ^ zp ^ ym, c1 = (zm & zp) | (ym & (zm ^ zp));
         const uint32_t s2 = yp ^ xm ^ xp, c2 = (yp & xm) | (xp & (yp ^ xm));
@@ -535,33 +664,11 @@ __device__ __forceinline__ void bp_march(const RepView &v, const Entry &en, int 
 
         const int cls = (x == 0 ? 1 : 0) + (x == Lx - 1 ? 2 : 0);
         const int k = 6 - (x == 0) - (x == Lx - 1);
-        const uint32_t gbase = row * (uint32_t)C + 8u * (uint32_t)w;
-        const TD *tdc = tb->td + cls * kThrPerClass;
-        const uint64_t *thc = tb->thr + cls * kThrPerClass;
-        uint32_t F = 0;
-#pragma unroll
-        for (int h = 0; h < 4; ++h) {
-            // eight sites 8h .. 8h+7: nibble i holds 8u + cnt of site 8h+i
-            const uint32_t nib = (spread_nibbles(S >> (8 * h)) << 3) | (spread_nibbles(b2 >> (8 * h)) << 2) |
-                                 (spread_nibbles(b1 >> (8 * h)) << 1) | spread_nibbles(b0 >> (8 * h));
-#pragma unroll
-            for (int g2 = 0; g2 < 2; ++g2) {
-                uint32_t rnd[4];
-                philox10(((gbase + (uint32_t)(2 * h + g2)) << 1) | (uint32_t)q, v.t, v.replica, 0u, v.key0,
-                         v.key1, rnd);
-#pragma unroll
-                for (int l = 0; l < 4; ++l) {
-                    const int i = 4 * g2 + l;
-                    const uint32_t e = (nib >> (4 * i)) & 0xFu;
-                    bool acc;
-                    if (NEVER) acc = (uint64_t)rnd[l] < thc[e];
-                    else acc = rnd[l] <= tdc[e].thr_m1;
-                    F |= (uint32_t)acc << (8 * h + i);
-                }
-            }
-        }
+        uint32_t F;
+        if (!NEVER && cls == 0) F = bp_flips_pairs(S, b2, b1, b0, gq, v, tb);
+        else F = bp_flips<NEVER>(S, b2, b1, b0, gq, v, tb, cls);
         F &= vmask;
-        wout[own] = S ^ F;
+        wout[own >> 2] = S ^ F;
         const uint32_t FU = F & S;
         const int nf = __popc(F), nfu = __popc(FU);
         const int Sf = __popc(F & b0) + 2 * __popc(F & b1) + 4 * __popc(F & b2);
@@ -572,14 +679,20 @@ __device__ __forceinline__ void bp_march(const RepView &v, const Entry &en, int 
         dM += dm;
         if (x == 0) a.dM1 += dm;
         if (x == Lx - 1) a.dMn += dm;
+        // the next plane: its x-1 word is this plane's other sublattice, its
+        // other-sublattice word is this plane's x+1 word
+        xm = O;
+        O = xp;
+        if (more) cur = nxt;
+        rw += XB;
+        gq += gstep;
+        gq ^= 1u;
+        q ^= 1;
     }
     a.dB += dB;
     a.dM += dM;
 }
 
-// ---------------------------------------------------------------------------
-// Processing of a contiguous range of work entries by one workgroup.
-// ---------------------------------------------------------------------------
 // ---------------------------------------------------------------------------
 // Sweep schedule.  The four phases of sweep t run in two launches:
 //   A(t): phase 3 of sweep t-1 on row 0, then phase 0 of sweep t;
@@ -706,7 +819,7 @@ __device__ __forceinline__ void main_entry(const RepDesc *__restrict__ descs, co
                                            const Entry &en, int k_lo, int k_hi, uint32_t s, Tables *tb)
 {
     const RepView v = load_view(descs, st, en.rep, s);
-    load_tables(descs[en.rep], tb);
+    load_tables<FMT == ISLF_SPIN_BITPACK>(descs[en.rep], tb);
     __syncthreads();
     Acc a = {0, 0, 0, 0};
     const int parity = KIND == KIND_A ? 0 : 1;
@@ -726,25 +839,40 @@ __device__ __forceinline__ void main_entry(const RepDesc *__restrict__ descs, co
     flush_acc(a, v.acc, v.t, blockIdx.x & (kAccSlots - 1));
 }
 
-// Launches A, B and F of sweep st.t + s.  Workgroups [0, n_slab) take one
-// slab entry each (first, so that the two-stage tiles start early), the rest
-// one main entry each (none in F).  With FLAG_FOLD, waves of B first fold
-// the previous sweep's record.
+// Workgroup b of a launch plan runs items [first[b'], first[b'+1]) in order,
+// where b' spreads consecutive plan blocks over the eight XCDs' dispatch
+// order so that each XCD (and its L2) works on a contiguous run of tiles.
+__device__ __forceinline__ int plan_block()
+{
+    const int b = blockIdx.x, G = gridDim.x;
+    return (G & 7) ? b : (b & 7) * (G >> 3) + (b >> 3);
+}
+
+template <int FMT, int KIND>
+__device__ __forceinline__ void run_items(const RepDesc *__restrict__ descs, const RepState *__restrict__ st,
+                                          const Entry *__restrict__ items, int i0, int i1, uint32_t s,
+                                          uint32_t flags, Tables *tb)
+{
+    for (int i = i0; i < i1; ++i) {
+        const Entry en = items[i];
+        if (en.kind == ITEM_SLAB) slab_entry<FMT, KIND>(descs, st, en, s, flags, tb);
+        else if (KIND != KIND_F) main_entry<FMT, KIND>(descs, st, en, 0, en.nsteps, s, tb);
+    }
+}
+
+// Launches A, B and F of sweep st.t + s over a launch plan (slab items come
+// first in the plan, so F only launches the blocks that hold them).  With
+// FLAG_FOLD, waves of B first fold the previous sweep's record.
 template <int FMT, int KIND>
 __global__ __launch_bounds__(kBlock) void k_sweep(const RepDesc *__restrict__ descs, RepState *__restrict__ st,
-                                                  const Entry *__restrict__ slabw, long n_slab,
-                                                  const Entry *__restrict__ mainw, const int *__restrict__ reps,
-                                                  int n_reps, uint32_t s, uint32_t flags)
+                                                  const Entry *__restrict__ items, const int *__restrict__ first,
+                                                  const int *__restrict__ reps, int n_reps, uint32_t s,
+                                                  uint32_t flags)
 {
     __shared__ Tables tb;
-    const long b = blockIdx.x;
     if (KIND == KIND_B && (flags & FLAG_FOLD)) fold_waves(descs, st, reps, n_reps, s - 1, 0u);
-    if (b < n_slab) {
-        slab_entry<FMT, KIND>(descs, st, slabw[b], s, flags, &tb);
-    } else if (KIND != KIND_F) {
-        const Entry en = mainw[b - n_slab];
-        main_entry<FMT, KIND>(descs, st, en, 0, en.nsteps, s, &tb);
-    }
+    const int b = plan_block();
+    run_items<FMT, KIND>(descs, st, items, first[b], first[b + 1], s, flags, &tb);
 }
 
 // Closes a run of sweeps: folds sweep st.t + s and advances the counters.
@@ -806,60 +934,27 @@ __device__ bool grid_barrier(GridSync *sync, unsigned long long nblocks, unsigne
     return ok != 0;
 }
 
-// First main entry whose steps reach past slot s (binary search).
-__device__ __forceinline__ long find_entry(const Entry *__restrict__ work, long n, long long s)
-{
-    long lo = 0, hi = n;
-    while (lo < hi) {
-        const long mid = (lo + hi) >> 1;
-        const Entry en = work[mid];
-        if (en.slot0 + en.nsteps <= s) lo = mid + 1;
-        else hi = mid;
-    }
-    return lo;
-}
-
-// The work of one launch kind inside the persistent kernel: slab entries go
-// round robin, the main entries' x steps are split evenly over the grid.
-template <int FMT, int KIND>
-__device__ void persistent_part(const RepDesc *__restrict__ descs, const RepState *__restrict__ st,
-                                const Entry *__restrict__ slabw, long n_slab, const Entry *__restrict__ mainw,
-                                long n_main, uint32_t s, uint32_t flags, Tables *tb)
-{
-    const long G = gridDim.x, b = blockIdx.x;
-    for (long e = b; e < n_slab; e += G) slab_entry<FMT, KIND>(descs, st, slabw[e], s, flags, tb);
-    if (KIND == KIND_F || n_main == 0) return;
-    const Entry tail = mainw[n_main - 1];
-    const long long S = tail.slot0 + tail.nsteps;
-    const long long s0 = b * S / G, s1 = (b + 1) * S / G;
-    for (long e = find_entry(mainw, n_main, s0); e < n_main; ++e) {
-        const Entry en = mainw[e];
-        if (en.slot0 >= s1) break;
-        const int k_lo = (int)max(0ll, s0 - en.slot0);
-        const int k_hi = (int)min((long long)en.nsteps, s1 - en.slot0);
-        if (k_lo < k_hi) main_entry<FMT, KIND>(descs, st, en, k_lo, k_hi, s, tb);
-    }
-}
-
 template <int FMT>
 __global__ __launch_bounds__(kBlock) void k_persistent(const RepDesc *__restrict__ descs,
                                                        RepState *__restrict__ st,
-                                                       const Entry *__restrict__ slabw, long n_slab,
-                                                       const Entry *__restrict__ mainw, long n_main,
+                                                       const Entry *__restrict__ items,
+                                                       const int *__restrict__ first,
                                                        const int *__restrict__ reps, int n_reps,
                                                        uint32_t n_sweeps, GridSync *sync)
 {
     __shared__ Tables tb;
     const unsigned long long G = gridDim.x;
+    const int b = plan_block();
+    const int i0 = first[b], i1 = first[b + 1];
     unsigned long long passed = 0;
     for (uint32_t s = 0; s < n_sweeps; ++s) {
-        persistent_part<FMT, KIND_A>(descs, st, slabw, n_slab, mainw, n_main, s, s ? FLAG_PREV : 0u, &tb);
+        run_items<FMT, KIND_A>(descs, st, items, i0, i1, s, s ? FLAG_PREV : 0u, &tb);
         if (!grid_barrier(sync, G, passed)) return;
         if (s > 0) fold_waves(descs, st, reps, n_reps, s - 1, 0u);
-        persistent_part<FMT, KIND_B>(descs, st, slabw, n_slab, mainw, n_main, s, 0u, &tb);
+        run_items<FMT, KIND_B>(descs, st, items, i0, i1, s, 0u, &tb);
         if (!grid_barrier(sync, G, passed)) return;
     }
-    persistent_part<FMT, KIND_F>(descs, st, slabw, n_slab, mainw, n_main, n_sweeps - 1, 0u, &tb);
+    run_items<FMT, KIND_F>(descs, st, items, i0, i1, n_sweeps - 1, 0u, &tb);
     if (!grid_barrier(sync, G, passed)) return;
     fold_waves(descs, st, reps, n_reps, n_sweeps - 1, n_sweeps);
 }
@@ -1088,36 +1183,53 @@ __global__ void k_integrate(const double *__restrict__ h, const double *__restri
 // ---------------------------------------------------------------------------
 // Host-callable launchers (used by islf_api.hip).
 // ---------------------------------------------------------------------------
-template <int FMT>
-static void launch_sweep_fmt(int kind, unsigned int grid, const RepDesc *descs, RepState *st, const Entry *slabw,
-                             long n_slab, const Entry *mainw, const int *reps, int n_reps, uint32_t s,
-                             uint32_t flags, hipStream_t strm)
-{
-    if (kind == KIND_A)
-        hipLaunchKernelGGL((k_sweep<FMT, KIND_A>), dim3(grid), dim3(kBlock), 0, strm, descs, st, slabw, n_slab,
-                           mainw, reps, n_reps, s, flags);
-    else if (kind == KIND_B)
-        hipLaunchKernelGGL((k_sweep<FMT, KIND_B>), dim3(grid), dim3(kBlock), 0, strm, descs, st, slabw, n_slab,
-                           mainw, reps, n_reps, s, flags);
-    else
-        hipLaunchKernelGGL((k_sweep<FMT, KIND_F>), dim3(grid), dim3(kBlock), 0, strm, descs, st, slabw, n_slab,
-                           mainw, reps, n_reps, s, flags);
-}
-
-// kind 0 = A, 1 = B (grid n_slab + n_main), 2 = F (grid n_slab)
-hipError_t launch_sweep(int fmt, int kind, const RepDesc *descs, RepState *st, const Entry *slabw, long n_slab,
-                        const Entry *mainw, long n_main, const int *reps, int n_reps, uint32_t s, uint32_t flags,
+// kind 0 = A, 1 = B, 2 = F; grid = the plan's blocks (F: its slab blocks)
+hipError_t launch_sweep(int fmt, int kind, const RepDesc *descs, RepState *st, const Entry *items,
+                        const int *first, int grid, const int *reps, int n_reps, uint32_t s, uint32_t flags,
                         hipStream_t strm)
 {
-    const long g = kind == KIND_F ? n_slab : n_slab + n_main;
-    if (g <= 0) return hipSuccess;
-    if (fmt == ISLF_SPIN_INT8)
-        launch_sweep_fmt<ISLF_SPIN_INT8>(kind, (unsigned int)g, descs, st, slabw, n_slab, mainw, reps, n_reps, s,
-                                         flags, strm);
-    else
-        launch_sweep_fmt<ISLF_SPIN_BITPACK>(kind, (unsigned int)g, descs, st, slabw, n_slab, mainw, reps, n_reps,
-                                            s, flags, strm);
+    if (grid <= 0) return hipSuccess;
+    const dim3 g((unsigned int)grid), blk(kBlock);
+    if (fmt == ISLF_SPIN_INT8) {
+        if (kind == KIND_A)
+            hipLaunchKernelGGL((k_sweep<ISLF_SPIN_INT8, KIND_A>), g, blk, 0, strm, descs, st, items, first, reps,
+                               n_reps, s, flags);
+        else if (kind == KIND_B)
+            hipLaunchKernelGGL((k_sweep<ISLF_SPIN_INT8, KIND_B>), g, blk, 0, strm, descs, st, items, first, reps,
+                               n_reps, s, flags);
+        else
+            hipLaunchKernelGGL((k_sweep<ISLF_SPIN_INT8, KIND_F>), g, blk, 0, strm, descs, st, items, first, reps,
+                               n_reps, s, flags);
+    } else {
+        if (kind == KIND_A)
+            hipLaunchKernelGGL((k_sweep<ISLF_SPIN_BITPACK, KIND_A>), g, blk, 0, strm, descs, st, items, first, reps,
+                               n_reps, s, flags);
+        else if (kind == KIND_B)
+            hipLaunchKernelGGL((k_sweep<ISLF_SPIN_BITPACK, KIND_B>), g, blk, 0, strm, descs, st, items, first, reps,
+                               n_reps, s, flags);
+        else
+            hipLaunchKernelGGL((k_sweep<ISLF_SPIN_BITPACK, KIND_F>), g, blk, 0, strm, descs, st, items, first, reps,
+                               n_reps, s, flags);
+    }
     return hipGetLastError();
+}
+
+// resident workgroups per CU of the A / B sweep kernels (the smaller)
+hipError_t sweep_blocks_per_cu(int fmt, int *per_cu)
+{
+    int a = 0, b = 0;
+    hipError_t e;
+    if (fmt == ISLF_SPIN_INT8) {
+        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&a, k_sweep<ISLF_SPIN_INT8, KIND_A>, kBlock, 0);
+        if (e == hipSuccess)
+            e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&b, k_sweep<ISLF_SPIN_INT8, KIND_B>, kBlock, 0);
+    } else {
+        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&a, k_sweep<ISLF_SPIN_BITPACK, KIND_A>, kBlock, 0);
+        if (e == hipSuccess)
+            e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&b, k_sweep<ISLF_SPIN_BITPACK, KIND_B>, kBlock, 0);
+    }
+    *per_cu = e == hipSuccess ? (a < b ? a : b) : 0;
+    return e;
 }
 
 hipError_t launch_fold(const RepDesc *descs, RepState *st, const int *reps, int n_reps, uint32_t s,
@@ -1135,11 +1247,10 @@ const void *persistent_kernel(int fmt)
                                  : (const void *)k_persistent<ISLF_SPIN_BITPACK>;
 }
 
-hipError_t launch_persistent(int fmt, const RepDesc *descs, RepState *st, const Entry *ws, long ns,
-                             const Entry *wm, long nm, const int *reps, int nreps, uint32_t nsweeps,
-                             GridSync *sync, int grid, hipStream_t s)
+hipError_t launch_persistent(int fmt, const RepDesc *descs, RepState *st, const Entry *items, const int *first,
+                             const int *reps, int nreps, uint32_t nsweeps, GridSync *sync, int grid, hipStream_t s)
 {
-    void *args[] = {(void *)&descs, (void *)&st, (void *)&ws, (void *)&ns, (void *)&wm, (void *)&nm,
+    void *args[] = {(void *)&descs, (void *)&st, (void *)&items, (void *)&first,
                     (void *)&reps, (void *)&nreps, (void *)&nsweeps, (void *)&sync};
     // fresh barrier counters for this launch (the error line is kept)
     hipLaunchKernelGGL(k_zero_u64, dim3(1), dim3(64), 0, s, (unsigned long long *)&sync->top, 16L);

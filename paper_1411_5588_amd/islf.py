@@ -110,6 +110,8 @@ def lib():
             "islf_get_tile": [vp, i32, P(i32)],
             "islf_set_tile": [vp, i32, i32],
             "islf_autotune": [vp, u32],
+            "islf_set_grid": [vp, i32],
+            "islf_get_grid": [vp, P(i32)],
             "islf_phase_timings": [vp, u32, vp, vp],
             "islf_replica_means": [vp, i32, u64, u32, vp],
         }
@@ -294,6 +296,15 @@ class Context:
 
     def autotune(self, sweeps=4):
         _check(lib().islf_autotune(self._h, sweeps))
+
+    def set_grid(self, workgroups: int):
+        """Workgroups per A / B launch (0 = two per resident slot)."""
+        _check(lib().islf_set_grid(self._h, workgroups))
+
+    def get_grid(self) -> int:
+        n = C.c_int32()
+        _check(lib().islf_get_grid(self._h, C.byref(n)))
+        return n.value
 
     def phase_timings(self, n_sweeps=4):
         """Mean ms per launch and launch counts of (A, B, closing F + fold):
