@@ -132,6 +132,7 @@ struct RepView {
     int seam_reflect, seam_invert;
     uint32_t key0, key1, replica, t;
     int tj, ty, mx;          // marching tile
+    int my_ty, my_tj;        // this thread's row and column inside the tile
     bool never;              // some move can never be accepted (thr == 0)
 };
 
@@ -151,6 +152,8 @@ __device__ __forceinline__ RepView load_view(const RepDesc *__restrict__ descs, 
     v.tj = d.i8_tj;
     v.ty = d.i8_ty;
     v.mx = d.i8_mx;
+    v.my_ty = (int)threadIdx.x / v.tj;
+    v.my_tj = (int)threadIdx.x - v.my_ty * v.tj;
     v.never = d.never_mask != 0;
     return v;
 }
@@ -384,9 +387,7 @@ template <bool NEVER, bool RAGGED>
 __device__ __forceinline__ void i8_march(const RepView &v, const Entry &en, int k_lo, int k_hi, int parity,
                                          const Tables *tb, Acc &a)
 {
-    const int tid = threadIdx.x;
-    const int ty = tid / v.tj;
-    const int tj = tid - ty * v.tj;
+    const int ty = v.my_ty, tj = v.my_tj;
     const int y = en.y0 + ty;
     const int j = en.j0 + tj;
     if (ty >= v.ty || y >= v.Ly - 1 || j >= v.C) return;   // main rows are 2 .. Ly-2
@@ -609,9 +610,7 @@ template <bool NEVER>
 __device__ __forceinline__ void bp_march(const RepView &v, const Entry &en, int k_lo, int k_hi, int parity,
                                          const Tables *tb, Acc &a)
 {
-    const int tid = threadIdx.x;
-    const int ty = tid / v.tj;
-    const int tj = tid - ty * v.tj;
+    const int ty = v.my_ty, tj = v.my_tj;
     const int y = en.y0 + ty;
     const int w = en.j0 + tj;
     if (ty >= v.ty || y >= v.Ly - 1 || w >= v.Wq) return;   // main rows are 2 .. Ly-2
@@ -812,16 +811,13 @@ __device__ __forceinline__ void slab_entry(const RepDesc *__restrict__ descs, co
     }
 }
 
-// One main entry (rows 2 .. Ly-2), x steps [k_lo, k_hi), of launch A
-// (phase 0) or B (phase 1) of sweep st.t + s; ends with a workgroup barrier.
+// One main tile piece (rows 2 .. Ly-2), x steps [k_lo, k_hi), of launch A
+// (phase 0) or B (phase 1), with the replica's view and tables in place;
+// adds its changes of the observables to a.
 template <int FMT, int KIND>
-__device__ __forceinline__ void main_entry(const RepDesc *__restrict__ descs, const RepState *__restrict__ st,
-                                           const Entry &en, int k_lo, int k_hi, uint32_t s, Tables *tb)
+__device__ __forceinline__ void main_piece(const RepView &v, const Entry &en, int k_lo, int k_hi, const Tables *tb,
+                                           Acc &a)
 {
-    const RepView v = load_view(descs, st, en.rep, s);
-    load_tables<FMT == ISLF_SPIN_BITPACK>(descs[en.rep], tb);
-    __syncthreads();
-    Acc a = {0, 0, 0, 0};
     const int parity = KIND == KIND_A ? 0 : 1;
     if (FMT == ISLF_SPIN_INT8) {
         const bool ragged = (v.Lz & 7) != 0;
@@ -836,7 +832,6 @@ __device__ __forceinline__ void main_entry(const RepDesc *__restrict__ descs, co
         if (v.never) bp_march<true>(v, en, k_lo, k_hi, parity, tb, a);
         else bp_march<false>(v, en, k_lo, k_hi, parity, tb, a);
     }
-    flush_acc(a, v.acc, v.t, blockIdx.x & (kAccSlots - 1));
 }
 
 // Workgroup b of a launch plan runs items [first[b'], first[b'+1]) in order,
@@ -853,11 +848,32 @@ __device__ __forceinline__ void run_items(const RepDesc *__restrict__ descs, con
                                           const Entry *__restrict__ items, int i0, int i1, uint32_t s,
                                           uint32_t flags, Tables *tb)
 {
-    for (int i = i0; i < i1; ++i) {
+    // a workgroup's slab items come before its main pieces; consecutive main
+    // pieces of one replica share the loaded view and tables and one flush
+    // of their summed changes
+    int i = i0;
+    for (; i < i1; ++i) {
         const Entry en = items[i];
-        if (en.kind == ITEM_SLAB) slab_entry<FMT, KIND>(descs, st, en, s, flags, tb);
-        else if (KIND != KIND_F) main_entry<FMT, KIND>(descs, st, en, 0, en.nsteps, s, tb);
+        if (en.kind != ITEM_SLAB) break;
+        slab_entry<FMT, KIND>(descs, st, en, s, flags, tb);
     }
+    if (KIND == KIND_F) return;
+    const int slot = blockIdx.x & (kAccSlots - 1);
+    int cur = -1;
+    RepView v;
+    Acc a = {0, 0, 0, 0};
+    for (; i < i1; ++i) {
+        const Entry en = items[i];
+        if (en.rep != cur) {
+            if (cur >= 0) flush_acc(a, v.acc, v.t, slot);   // its barrier frees the tables
+            v = load_view(descs, st, en.rep, s);
+            load_tables<FMT == ISLF_SPIN_BITPACK>(descs[en.rep], tb);
+            __syncthreads();
+            cur = en.rep;
+        }
+        main_piece<FMT, KIND>(v, en, 0, en.nsteps, tb, a);
+    }
+    if (cur >= 0) flush_acc(a, v.acc, v.t, slot);
 }
 
 // Launches A, B and F of sweep st.t + s over a launch plan (slab items come
