@@ -23,6 +23,7 @@
  *    and thr = 2^32 if dE <= 0 else floor(2^32 exp(-beta dE)).
  *  - Observables (Eq. 7 and Eq. 19 integrands): bond sum B, magnetisation M,
  *    surface-layer sums M1 (x = 0) and Mn (x = Lx-1), recomputed in full.
+ *  - Layer profile (Eq. 17): the sum over z of the spins of every (x, y) row.
  *  - Thermodynamic integration over the surface field (Eq. 9, Eq. 22) by the
  *    trapezoid rule.
  *
@@ -336,6 +337,18 @@ void oracle_observables(const or_lattice *L, const int8_t *s, int64_t out[4])
         if (x == L->Lx - 1) Mn += s[i];
     }
     out[0] = B; out[1] = M; out[2] = M1; out[3] = Mn;
+}
+
+/* Layer profile (Sec. II.B, Eq. 17): out[x*Ly + y] = sum over z of S(x, y, z),
+ * i.e. Lz times the paper's row magnetisation m_{k_x}(y). */
+void oracle_layer_profile(const or_lattice *L, const int8_t *s, int64_t *out)
+{
+    for (int64_t r = 0; r < (int64_t)L->Lx * L->Ly; ++r) out[r] = 0;
+    for (int64_t i = 0; i < L->N; ++i) {
+        int64_t x, y, z;
+        or_coords(L, i, &x, &y, &z);
+        out[x * L->Ly + y] += s[i];
+    }
 }
 
 /* E = -J B - H M - h1 M1 - hn Mn (Eq. 1), evaluated left to right in FP64. */

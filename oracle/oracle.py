@@ -8,8 +8,9 @@ the Hamiltonian of Sec. II.A Eq. 1 with free x-surfaces carrying fields h1
 (x = 0, the paper's layer 1) and hn (x = Lx-1, layer n), periodic z, and a y
 boundary that is periodic, antiperiodic or the generalized antiperiodic
 condition of Eq. 11; checkerboard Metropolis sweeps (Appendix) with Philox
-draws; full-recompute observables (Eq. 7, Eq. 19 integrands) and the
-trapezoid thermodynamic integration of Eq. 9 / Eq. 22.
+draws; full-recompute observables (Eq. 7, Eq. 19 integrands), the layer
+profile of Eq. 17 and the trapezoid thermodynamic integration of Eq. 9 /
+Eq. 22.
 """
 from __future__ import annotations
 
@@ -77,6 +78,7 @@ def lib():
         L.oracle_mean.argtypes = [vp, i64, i64]
         L.oracle_integrate.argtypes = [vp, vp, vp, i32, dbl, dbl, dbl, vp]
         L.oracle_philox.argtypes = [vp, vp, vp]
+        L.oracle_layer_profile.argtypes = [vp, vp, vp]
         _lib = L
     return _lib
 
@@ -202,6 +204,13 @@ class Lattice:
 
     def energy(self, obs) -> float:
         return energy(self.J, self.H, self.h1, self.hn, obs)
+
+    def layer_profile(self, s=None) -> np.ndarray:
+        """(Lx, Ly) int64: sum over z of the spins of each row (Eq. 17 times Lz)."""
+        s = self.s if s is None else np.ascontiguousarray(s, dtype=np.int8)
+        out = np.zeros(self.Lx * self.Ly, dtype=np.int64)
+        lib().oracle_layer_profile(self._h, _ptr(s), _ptr(out))
+        return out.reshape(self.Lx, self.Ly)
 
     def spins3d(self) -> np.ndarray:
         return self.s.reshape(self.Lx, self.Ly, self.Lz)

@@ -1,0 +1,140 @@
+"""Pins of the host-side FP64 analysis (Sec. II.B, II.C).
+
+Each formula is checked against something the paper or the mathematics fixes
+independently of how it is coded: a synthetic film whose dividing plane is
+known (Eqs. 17, 18), closed-form solutions of the modified Young equation
+(Eq. 16), exact line fits (Eq. 20), an exact balance of Eqs. 21-22, and the
+free-energy difference of two boundary conditions from exact enumeration
+(Eqs. 19, 20).
+"""
+import math
+
+import numpy as np
+import pytest
+
+from oracle import enumerate_exact as X
+from paper_1411_5588_amd import analysis as A
+
+
+def synthetic_film(Lx, Ly, y0, slope, m_plus, m_minus):
+    """Row magnetisations of a film whose + domain covers y < y0 + slope * x,
+    with the boundary row filled in proportion."""
+    m = np.empty((Lx, Ly))
+    for x in range(Lx):
+        yb = y0 + slope * x
+        for y in range(Ly):
+            f = min(1.0, max(0.0, yb - y))
+            m[x, y] = f * m_plus[x] + (1.0 - f) * m_minus[x]
+    return m
+
+
+@pytest.mark.parametrize("slope", [0.0, 0.35, -0.8, 2.5])
+def test_dividing_plane_and_angle(slope):
+    Lx, Ly = 14, 120
+    mp = 0.9 - 0.01 * np.arange(Lx)
+    mm = -0.85 + 0.005 * np.arange(Lx)
+    y0 = 45.3 if slope >= 0 else 75.6
+    m = synthetic_film(Lx, Ly, y0, slope, mp, mm)
+    mbar = A.layer_means(m)
+    yp = A.dividing_surface(mbar, mp, mm, Ly)
+    assert np.allclose(yp, y0 + slope * np.arange(Lx), rtol=0, atol=1e-11)
+    theta, a, b = A.contact_angle(yp)
+    assert abs(b - slope) < 1e-12 and abs(a - y0) < 1e-10
+    assert abs(theta - math.atan2(1.0, abs(slope))) < 1e-12
+    # plateaus found from the profile itself
+    p, q = A.plateau_values(m, 0.1)
+    assert np.allclose(p, mp, atol=1e-14) and np.allclose(q, mm, atol=1e-14)
+
+
+def test_profile_end_to_end():
+    Lx, Ly, Lz, count = 10, 80, 16, 7
+    mp, mm = np.full(Lx, 0.75), np.full(Lx, -0.75)
+    m = synthetic_film(Lx, Ly, 30.25, 1.5, mp, mm)
+    acc = m * Lz * count           # what an accumulated profile holds
+    r = A.contact_angle_from_profile(acc, count, Lz)
+    assert abs(r["theta"] - math.atan2(1.0, 1.5)) < 1e-12
+    assert abs(r["slope"] - 1.5) < 1e-12
+
+
+def test_young_isotropic_recovers_constant_tension():
+    # isotropic gamma: Young's equation holds, delta_f1 = gamma cos(theta);
+    # the modified-Young integral must return gamma at every angle
+    g0 = 0.83
+    theta = np.linspace(math.pi / 2, 0.35, 4001)
+    df = g0 * np.cos(theta)
+    g = A.young_gamma(theta, df, g0)
+    assert np.max(np.abs(g - g0)) < 2e-7
+    # the trapezoid error shrinks fourfold when the path is refined
+    theta2 = np.linspace(math.pi / 2, 0.35, 2001)
+    e2 = np.max(np.abs(A.young_gamma(theta2, g0 * np.cos(theta2), g0) - g0))
+    e1 = np.max(np.abs(g - g0))
+    assert 3.5 < e2 / e1 < 4.5
+    assert np.allclose(A.young_angle(df, g0), theta, atol=1e-12)
+
+
+def test_young_linear_in_cot_is_exact():
+    # delta_f1 = k cot(theta)  =>  gamma / sin(theta) = g0 + k cot^2(theta) / 2
+    g0, k = 1.1, -0.37
+    theta = np.array([math.pi / 2, 1.4, 1.2, 1.0, 0.8, 0.6])
+    c = np.cos(theta) / np.sin(theta)
+    g = A.young_gamma(theta, k * c, g0)
+    want = np.sin(theta) * (g0 + 0.5 * k * c ** 2)
+    assert np.allclose(g, want, rtol=1e-13, atol=1e-15)
+    # and it satisfies the differential equation (central differences)
+    th = np.linspace(1.5, 0.7, 801)
+    cc = np.cos(th) / np.sin(th)
+    gg = np.sin(th) * (g0 + 0.5 * k * cc ** 2)
+    dg = np.gradient(gg, th)
+    resid = gg * np.cos(th) - dg * np.sin(th) - k * cc
+    assert np.max(np.abs(resid[2:-2])) < 1e-5
+
+
+def test_tension_from_sizes_exact():
+    gamma, tau = 0.612, -0.21
+    Lx = np.array([24, 48, 96])
+    v = gamma + 2.0 * tau / Lx
+    g, t = A.tension_from_sizes(Lx, v)
+    assert abs(g - gamma) < 1e-14 and abs(t - tau) < 1e-13
+
+
+def test_line_tension_balance():
+    Lx, Ly, Lz = 48, 288, 96
+    theta = np.array([1.2, 0.9])
+    gth = np.array([0.7, 0.75])
+    g90, ssum, sdiff = 0.61, np.array([0.01, 0.03]), np.array([-0.2, -0.35])
+    dtau = np.array([-0.05, -0.11])
+    ti = (Lx * Lz * (gth / np.sin(theta) - g90) + Lz * Ly * ssum
+          + Lz * Lx * sdiff / np.tan(theta) + 2 * Lz * dtau)
+    got = A.line_tension_shift(Lx, Ly, Lz, theta, gth, g90, ssum, sdiff, ti)
+    assert np.allclose(got, dtau, rtol=0, atol=1e-12)
+
+
+def _exact_ladder(shape, ybc, betas):
+    S = X.all_states(*shape)
+    E = X.energies(X.observables(S, ybc), 1.0, 0.0, 0.0, 0.0)
+    U, lnZ = [], []
+    for b in betas:
+        a = -b * E
+        am = a.max()
+        w = np.exp(a - am)
+        U.append(float((w * E).sum() / w.sum()))
+        lnZ.append(float(np.log(w.sum()) + am))
+    return np.array(U), np.array(lnZ)
+
+
+def test_delta_free_energy_matches_enumeration():
+    # Eq. 19 for both films from beta_0 = 0 (where Z = 2^N for either boundary
+    # condition, so beta_0 delta F(beta_0) = 0 exactly) against -ln Z
+    shape = (2, 3, 2)
+    b_end = 0.9
+    errs = []
+    for n in (401, 801):
+        betas = np.linspace(0.0, b_end, n)
+        Ua, lza = _exact_ladder(shape, X.APBC, betas)
+        Up, lzp = _exact_ladder(shape, X.PBC, betas)
+        dF = A.delta_free_energy(betas[1:], Ua[1:], Up[1:],
+                                 beta_dF0=0.5 * (betas[1] - betas[0]) * ((Ua[0] - Up[0]) + (Ua[1] - Up[1])))
+        exact = -(lza[1:] - lzp[1:]) / betas[1:]
+        errs.append(np.max(np.abs(dF - exact)[n // 10:]) / np.max(np.abs(exact)))
+    assert errs[1] < 5e-6
+    assert 3.5 < errs[0] / errs[1] < 4.5
