@@ -234,6 +234,18 @@ islf_status islf_get_tile(const islf_ctx *ctx, int32_t rep, int32_t *tile);
 islf_status islf_set_tile(islf_ctx *ctx, int32_t rep, int32_t tile);
 islf_status islf_autotune(islf_ctx *ctx, uint32_t sweeps);
 
+/* Layer profile of one replica's current spins (Sec. II.B, Eq. 17): for
+ * every row (x, y), P[x*Ly + y] = sum over z of S(x, y, z), i.e. Lz times the
+ * paper's row magnetisation m_{k_x}(y).  islf_layer_profile writes P to
+ * dev_out (device memory, Lx*Ly int32, caller-owned); islf_layer_profile_add
+ * adds P to dev_acc (device memory, Lx*Ly int64, caller-owned) so that a
+ * sampled average accumulates on the device.  Both are enqueued on the
+ * context's stream after the work issued before them and do not
+ * synchronise.  Errors: EINVAL (NULL pointer), ERANGE (replica not live),
+ * EDEVICE. */
+islf_status islf_layer_profile(islf_ctx *ctx, int32_t rep, int32_t *dev_out);
+islf_status islf_layer_profile_add(islf_ctx *ctx, int32_t rep, int64_t *dev_acc);
+
 /* Workgroups per A / B launch of the batched and plain forms; the work of a
  * launch is split evenly over them.  0 (the default) means two per resident
  * slot of the sweep kernels on the device; islf_get_grid reports the value in

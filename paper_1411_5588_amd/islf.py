@@ -111,6 +111,8 @@ def lib():
             "islf_set_tile": [vp, i32, i32],
             "islf_autotune": [vp, u32],
             "islf_set_grid": [vp, i32],
+            "islf_layer_profile": [vp, i32, vp],
+            "islf_layer_profile_add": [vp, i32, vp],
             "islf_get_grid": [vp, P(i32)],
             "islf_phase_timings": [vp, u32, vp, vp],
             "islf_replica_means": [vp, i32, u64, u32, vp],
@@ -296,6 +298,31 @@ class Context:
 
     def autotune(self, sweeps=4):
         _check(lib().islf_autotune(self._h, sweeps))
+
+    def _enqueue_on_ctx(self, fn):
+        # caller tensors come from torch's current stream: the context's stream
+        # waits for it before the kernel, and later work on the current stream
+        # waits for the kernel
+        cur = self.torch.cuda.current_stream()
+        self.stream.wait_stream(cur)
+        fn()
+        cur.wait_stream(self.stream)
+
+    def layer_profile(self, rep: int, out=None):
+        """Row sums over z of replica rep's current spins (Eq. 17 times Lz): a
+        (Lx, Ly) int32 device tensor, ordered before later work on torch's
+        current stream."""
+        _, (Lx, Ly, _) = self._N(rep)
+        if out is None:
+            out = self.torch.empty((Lx, Ly), dtype=self.torch.int32, device="cuda")
+        self._enqueue_on_ctx(lambda: _check(lib().islf_layer_profile(self._h, rep, C.c_void_p(out.data_ptr()))))
+        return out
+
+    def layer_profile_add(self, rep: int, acc):
+        """Adds replica rep's row sums to the (Lx, Ly) int64 device tensor acc."""
+        self._enqueue_on_ctx(lambda: _check(lib().islf_layer_profile_add(self._h, rep,
+                                                                       C.c_void_p(acc.data_ptr()))))
+        return acc
 
     def set_grid(self, workgroups: int):
         """Workgroups per A / B launch (0 = two per resident slot)."""

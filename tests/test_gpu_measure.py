@@ -53,11 +53,9 @@ def test_means_and_ti_pipeline_match_oracle():
     outs = parallel_map(lambda p: oracle_trajectory(p, n)[1], ps)
     for r, o_rec in enumerate(outs):
         om = [O.mean(o_rec, k, first=t0) for k in range(4)]
-        oE = O.energy(ps[r]["J"], ps[r]["H"], ps[r]["h1"], ps[r]["hn"], np.zeros(4))  # shape check only
         assert np.array_equal(means[r, 1:], om), r
         e_ref = ((-ps[r]["J"] * om[0] - ps[r]["H"] * om[1]) - ps[r]["h1"] * om[2]) - ps[r]["hn"] * om[3]
         assert means[r, 0] == e_ref
-        del oE
     o_m1 = np.array([O.mean(o, 2, first=t0) for o in outs])
     o_mn = np.array([O.mean(o, 3, first=t0) for o in outs])
     ref = O.integrate(hs, o_m1, o_mn, -1.0, 1.0, norm)
