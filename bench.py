@@ -110,6 +110,32 @@ def run_form(islf, torch, form, fmt, steps, warmup, chunk, timings=False):
         ctx.close()
 
 
+def layer_profile_rate(islf, torch, calls=20):
+    """The layer-profile reduction (Eq. 17) on one bit-packed replica of the
+    workload: microseconds per call (HIP events on the context's stream) and
+    the spin bytes it reads per second."""
+    Lx, Ly, Lz = SHAPE
+    with islf.Context(replicas(islf)[:1], spin_format=islf.BITPACK, obs_capacity=8) as ctx:
+        acc = torch.zeros((Lx, Ly), dtype=torch.int64, device="cuda")
+        ctx.sweep(2)
+        ctx.layer_profile_add(0, acc)
+        s = ctx.stream
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        # back-to-back launches on the context's stream (no host round trips
+        # between them), bracketed by events on that stream
+        ptr = islf.C.c_void_p(acc.data_ptr())
+        e0.record(s)
+        for _ in range(calls):
+            islf.lib().islf_layer_profile_add(ctx._h, 0, ptr)
+        e1.record(s)
+        torch.cuda.synchronize()
+        us = e0.elapsed_time(e1) * 1e3 / calls
+    spin_bytes = Lx * Ly * 2 * 4 * ((Lz + 63) // 64)
+    return {"us_per_call": round(us, 2), "spin_GBs": round(spin_bytes / (us * 1e-6) / 1e9, 1),
+            "replica": f"{Lx}x{Ly}x{Lz} bit-packed"}
+
+
 def kernel_source_hash():
     with open(KERNEL_SOURCE, "rb") as f:
         return hashlib.sha256(f.read()).hexdigest()[:16]
@@ -218,6 +244,9 @@ def main():
                                                       / (main_ms * 1e-3) / 1e9, 1),
                              "peak_GBs": HBM_PEAK_GBS}}
 
+    prof = layer_profile_rate(islf, torch)
+    print(f"# layer profile: {prof}", file=sys.stderr, flush=True)
+
     cpu = None if args.no_cpu else cpu_baseline(args.cpu_sweeps)
     line = {
         "metric": "spin updates/ns", "value": round(value, 2), "unit": "spin updates/ns", "n_gpus": 1,
@@ -230,6 +259,7 @@ def main():
                    "sites_per_replica": N, "replicas": n_reps, "form": args.form, "spin_format": args.fmt},
         "forms": forms,
         "roofline": roofline,
+        "layer_profile": prof,
         "cpu_baseline": cpu,
     }
     print(json.dumps(line), flush=True)

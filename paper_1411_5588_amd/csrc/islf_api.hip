@@ -31,8 +31,8 @@ hipError_t launch_export(const RepDesc *descs, int rep, int8_t *out, hipStream_t
 hipError_t launch_recompute(const RepDesc *descs, int rep, const int8_t *spins, unsigned long long *out,
                             hipStream_t s);
 hipError_t launch_set_state(RepState *st, int rep, const unsigned long long *obs, uint32_t t, hipStream_t s);
-hipError_t launch_layer_profile(const RepDesc *descs, int rep, long rows, int32_t *out, long long *acc,
-                                hipStream_t s);
+hipError_t launch_layer_profile(const RepDesc *descs, int rep, long rows, long words_per_row, int32_t *out,
+                                long long *acc, hipStream_t s);
 hipError_t launch_zero(unsigned long long *p, long n, hipStream_t s);
 hipError_t launch_energy(const islf_obs *rec, uint32_t cap, uint64_t first, uint32_t count, double J,
                          double H, double h1, double hn, double *out, hipStream_t s);
@@ -1238,6 +1238,12 @@ extern "C" islf_status islf_autotune(islf_ctx *ctx, uint32_t sweeps)
     return sync_tables(ctx);
 }
 
+// 32-bit words per (x, y) row of the spin array
+static long profile_row_words(const Replica &R)
+{
+    return R.d.fmt == ISLF_SPIN_INT8 ? R.d.Lzp / 4 : 2l * R.d.Wq;
+}
+
 extern "C" islf_status islf_layer_profile(islf_ctx *ctx, int32_t rep, int32_t *dev_out)
 {
     islf_status st = check_rep(ctx, rep);
@@ -1246,7 +1252,8 @@ extern "C" islf_status islf_layer_profile(islf_ctx *ctx, int32_t rep, int32_t *d
     st = sync_tables(ctx);
     if (st != ISLF_OK) return st;
     const Replica &R = ctx->reps[rep];
-    HIP_TRY(launch_layer_profile(ctx->d_desc, rep, (long)R.desc.Lx * R.desc.Ly, dev_out, nullptr, ctx->stream));
+    HIP_TRY(launch_layer_profile(ctx->d_desc, rep, (long)R.desc.Lx * R.desc.Ly, profile_row_words(R), dev_out,
+                                 nullptr, ctx->stream));
     return ISLF_OK;
 }
 
@@ -1258,8 +1265,8 @@ extern "C" islf_status islf_layer_profile_add(islf_ctx *ctx, int32_t rep, int64_
     st = sync_tables(ctx);
     if (st != ISLF_OK) return st;
     const Replica &R = ctx->reps[rep];
-    HIP_TRY(launch_layer_profile(ctx->d_desc, rep, (long)R.desc.Lx * R.desc.Ly, nullptr, (long long *)dev_acc,
-                                 ctx->stream));
+    HIP_TRY(launch_layer_profile(ctx->d_desc, rep, (long)R.desc.Lx * R.desc.Ly, profile_row_words(R), nullptr,
+                                 (long long *)dev_acc, ctx->stream));
     return ISLF_OK;
 }
 

@@ -1111,46 +1111,52 @@ __global__ void k_recompute(const RepDesc *__restrict__ descs, int rep, const in
 // Sets the running observables of a replica (after init / set_spins).
 // Layer profile (Sec. II.B, Eq. 17): for every row (x, y) of replica rep,
 // P = sum over z of its spins, written to out (int32) or, if out is NULL,
-// added to acc (int64).  One wave per row: lanes read the row's 32-bit words
-// (int8: four sites per word; bit-packed: 32 sites of one sublattice) and
-// mask the padding past Lz; P = 2 * (up spins) - Lz.
+// added to acc (int64).  A workgroup owns R whole rows (R * words per row <=
+// 1024 words, at least one row) and reads them as one coalesced run of 32-bit
+// words (int8: four sites per word; bit-packed: 32 sites of one sublattice),
+// masks the padding past Lz, and sums the up spins of each row in LDS;
+// P = 2 * (up spins) - Lz.
+constexpr int kProfileWords = 1024;
+constexpr int kProfileRows = kProfileWords / 2;   // rows hold at least two words
+
 __global__ __launch_bounds__(256) void k_layer_profile(const RepDesc *__restrict__ descs, int rep,
                                                        int32_t *__restrict__ out, long long *__restrict__ acc)
 {
+    __shared__ uint32_t cnt[kProfileRows];
     const RepDesc &d = descs[rep];
-    const int lane = threadIdx.x & 63;
-    const long rows = (long)d.Lx * (long)d.Ly;
-    const long nwaves = (long)gridDim.x * (blockDim.x >> 6);
     const int Lz = d.Lz;
-    for (long r = (long)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6); r < rows; r += nwaves) {
-        uint32_t up = 0;
-        if (d.fmt == ISLF_SPIN_INT8) {
-            const gcu32 *row = (const gcu32 *)((const gcu8 *)d.spins + (size_t)r * (size_t)d.Lzp);
-            const int nw = d.Lzp >> 2;
-            for (int k = lane; k < nw; k += 64) {
-                uint32_t w = row[k];
-                const int z0 = 4 * k;
-                if (z0 + 4 > Lz) w &= (z0 >= Lz) ? 0u : ((1u << (8 * (Lz - z0))) - 1u);
-                up += __builtin_amdgcn_sad_u8(w, 0u, 0u);
-            }
+    const bool i8 = d.fmt == ISLF_SPIN_INT8;
+    const uint32_t rw = i8 ? (uint32_t)(d.Lzp >> 2) : (uint32_t)(2 * d.Wq);   // words per row
+    const long rows = (long)d.Lx * (long)d.Ly;
+    const uint32_t R = rw >= (uint32_t)kProfileWords ? 1u : (uint32_t)kProfileWords / rw;
+    const long r0 = (long)blockIdx.x * R;
+    if (r0 >= rows) return;
+    const uint32_t nr = (uint32_t)min((long)R, rows - r0);
+    for (uint32_t k = threadIdx.x; k < nr; k += blockDim.x) cnt[k] = 0;
+    __syncthreads();
+    const gcu32 *base = (const gcu32 *)d.spins + (size_t)r0 * rw;
+    const uint32_t nw = nr * rw;
+    const int Wq = d.Wq, nbits = Lz >> 1;
+    for (uint32_t k = threadIdx.x; k < nw; k += blockDim.x) {
+        const uint32_t row = k / rw, col = k - row * rw;
+        uint32_t v = base[k], up;
+        if (i8) {
+            const int z0 = 4 * (int)col;
+            if (z0 + 4 > Lz) v &= (z0 >= Lz) ? 0u : ((1u << (8 * (Lz - z0))) - 1u);
+            up = __builtin_amdgcn_sad_u8(v, 0u, 0u);
         } else {
-            const int Wq = d.Wq, nbits = Lz >> 1;
-            const gcu32 *row = (const gcu32 *)d.spins + (size_t)r * (size_t)(2 * Wq);
-            for (int k = lane; k < 2 * Wq; k += 64) {
-                const int w = k < Wq ? k : k - Wq;
-                const int nb = min(32, nbits - 32 * w);
-                uint32_t v = row[k];
-                if (nb < 32) v &= (1u << nb) - 1u;
-                up += (uint32_t)__popc(v);
-            }
+            const int w = (int)col < Wq ? (int)col : (int)col - Wq;
+            const int nb = min(32, nbits - 32 * w);
+            if (nb < 32) v &= (1u << nb) - 1u;
+            up = (uint32_t)__popc(v);
         }
-#pragma unroll
-        for (int off = 32; off > 0; off >>= 1) up += __shfl_xor(up, off, 64);
-        if (lane == 0) {
-            const int32_t P = 2 * (int32_t)up - Lz;
-            if (out) out[r] = P;
-            else acc[r] += P;
-        }
+        if (up) atomicAdd(&cnt[row], up);
+    }
+    __syncthreads();
+    for (uint32_t k = threadIdx.x; k < nr; k += blockDim.x) {
+        const int32_t P = 2 * (int32_t)cnt[k] - Lz;
+        if (out) out[r0 + k] = P;
+        else acc[r0 + k] += P;
     }
 }
 
@@ -1345,13 +1351,15 @@ hipError_t launch_recompute(const RepDesc *descs, int rep, const int8_t *spins, 
     return hipGetLastError();
 }
 
-hipError_t launch_layer_profile(const RepDesc *descs, int rep, long rows, int32_t *out, long long *acc,
-                                hipStream_t s)
+hipError_t launch_layer_profile(const RepDesc *descs, int rep, long rows, long words_per_row, int32_t *out,
+                                long long *acc, hipStream_t s)
 {
     if (rows <= 0) return hipSuccess;
-    const long blocks = (rows + 3) / 4;
-    const unsigned int grid = (unsigned int)(blocks < 8192 ? blocks : 8192);
-    hipLaunchKernelGGL(k_layer_profile, dim3(grid), dim3(256), 0, s, descs, rep, out, acc);
+    // the kernel's rows per workgroup: kProfileWords / words per row, at least 1
+    const long rw = words_per_row;
+    const long R = rw >= kProfileWords ? 1 : kProfileWords / rw;
+    const long grid = (rows + R - 1) / R;
+    hipLaunchKernelGGL(k_layer_profile, dim3((unsigned int)grid), dim3(256), 0, s, descs, rep, out, acc);
     return hipGetLastError();
 }
 
