@@ -361,15 +361,16 @@ struct StepIn {
     uint32_t pb, nb;
 };
 
-__device__ __forceinline__ StepIn load_step(const RepView &v, const MarchLane &L, const gcu8 *base, int x,
+// xo: byte offset of plane x in the replica's spin array
+__device__ __forceinline__ StepIn load_step(const RepView &v, const MarchLane &L, uint32_t xo, int x,
                                             uint32_t xstride)
 {
     StepIn in;
-    in.Wn = (x + 1 < v.Lx) ? *(gcu64 *)(base + xstride + L.oc) : 0ull;
-    in.Yp = *(gcu64 *)(base + L.oyp);
-    in.Ym = *(gcu64 *)(base + L.oym);
-    in.pb = *(base + L.oprev);
-    in.nb = *(base + L.onext);
+    in.Wn = (x + 1 < v.Lx) ? ld64(v.spins, xo + xstride + L.oc) : 0ull;
+    in.Yp = ld64(v.spins, xo + L.oyp);
+    in.Ym = ld64(v.spins, xo + L.oym);
+    in.pb = (uint32_t)ld8(v.spins, xo + L.oprev);
+    in.nb = (uint32_t)ld8(v.spins, xo + L.onext);
     return in;
 }
 
@@ -410,20 +411,20 @@ __device__ __forceinline__ void i8_march(const RepView &v, const Entry &en, int 
     L.valid = (L.r == 8) ? ~0ull : ((1ull << (8 * L.r)) - 1ull);
     L.padidx = ~L.valid & (0x0101010101010101ull * (uint64_t)(4 * kPadEntry));
 
-    const gcu8 *base = (gcu8 *)v.spins + (size_t)x0 * xstride;
+    uint32_t xo = (uint32_t)x0 * xstride;   // byte offset of plane x (a replica is below 4 GiB)
     const uint32_t gstep = 2u * (uint32_t)Ly * (uint32_t)C;
     int q = (parity + x0 + y) & 1;
     uint32_t g = ((((uint32_t)x0 * (uint32_t)Ly + (uint32_t)y) * (uint32_t)C + (uint32_t)j) << 1) | (uint32_t)q;
 
-    uint64_t Wc = *(gcu64 *)(base + L.oc);
-    uint64_t Wm = (x0 > 0) ? *(gcu64 *)(base - xstride + L.oc) : 0ull;
-    StepIn cur = load_step(v, L, base, x0, xstride);
+    uint64_t Wc = ld64(v.spins, xo + L.oc);
+    uint64_t Wm = (x0 > 0) ? ld64(v.spins, xo - xstride + L.oc) : 0ull;
+    StepIn cur = load_step(v, L, xo, x0, xstride);
     int dsum = 0, d1 = 0, dn = 0;
     for (int x = x0; x < x1; ++x) {
         // next step's neighbours first: independent of this step's result
         StepIn nxt;
         const bool more = x + 1 < x1;
-        if (more) nxt = load_step(v, L, base + xstride, x + 1, xstride);
+        if (more) nxt = load_step(v, L, xo + xstride, x + 1, xstride);
         uint64_t cnt = ((Wc << 8) | (uint64_t)cur.pb) + ((Wc >> 8) | ((uint64_t)cur.nb << (8 * (L.r - 1))));
         cnt += cur.Yp + cur.Ym;
         cnt += Wm + cur.Wn;
@@ -450,14 +451,14 @@ __device__ __forceinline__ void i8_march(const RepView &v, const Entry &en, int 
         const uint32_t fhi = (acc[2] ? 1u : 0u) | (acc[3] ? 0x10000u : 0u);
         uint64_t flip = ((uint64_t)fhi << 32 | flo) << (8 * q);
         if (RAGGED) flip &= L.valid;
-        *(gu64 *)((gcu8 *)base + L.oc) = Wc ^ flip;
+        *(gu64 *)((gcu8 *)v.spins + (xo + L.oc)) = Wc ^ flip;
         dsum += step;
         if (x == 0) d1 += step;
         if (x == Lx - 1) dn += step;
         Wm = Wc;
         Wc = cur.Wn;
         if (more) cur = nxt;
-        base += xstride;
+        xo += xstride;
         g += gstep;
         g ^= 1u;
         q ^= 1;
@@ -543,9 +544,8 @@ __device__ __forceinline__ uint32_t bp_flips_pairs(uint32_t S, uint32_t b2, uint
     transpose8x8(w[0], w[1]);
     transpose8x8(w[2], w[3]);
     uint32_t F = 0;
-    // not unrolled (keeps two draws live at a time); w[0] always holds the
-    // current iteration's pair indices
-#pragma unroll 1
+    // w[0] always holds the current iteration's pair indices
+#pragma unroll
     for (int g = 0; g < 4; ++g) {
         uint32_t r0[4], r1[4];
         philox10(gq + 2u * (uint32_t)g, v.t, v.replica, 0u, v.key0, v.key1, r0);
