@@ -392,6 +392,8 @@ static void free_plan(islf_ctx *c, Plan &p)
     p = Plan();
 }
 
+constexpr double kTailTaper = 0.2;
+
 // Splits the work into about `grid` runs of equal cost, one per workgroup:
 // workgroup b gets items [first[b], first[b+1]).  The slab items are spread
 // over the first min(grid, #slab) workgroups (so that a final launch of
@@ -419,8 +421,18 @@ static int partition_items(const std::vector<Entry> &slab, const std::vector<Ent
     size_t mi = 0;   // next main tile and x offset inside it
     int off = 0;
     long long acc = 0;
+    // cumulative cost targets: run r goes to the workgroup dispatched at rank
+    // d(r) (the inverse of the kernel's XCD-contiguous mapping); later ranks
+    // get smaller shares, weight 1 + a (1 - 2 u) at u = (d + 0.5) / grid
+    const double a = kTailTaper;
+    std::vector<double> cum(grid + 1, 0.0);
+    for (int r = 0; r < grid; ++r) {
+        const long d = (grid % 8) ? r : (long)(r % (grid / 8)) * 8 + r / (grid / 8);
+        const double u = (d + 0.5) / grid;
+        cum[r + 1] = cum[r] + 1.0 + a * (1.0 - 2.0 * u);
+    }
     for (int b = 0; b < grid; ++b) {
-        const long long target = (long long)((double)W * (b + 1) / grid);
+        const long long target = (long long)((double)W * cum[b + 1] / cum[grid]);
         if (b < gs)
             for (long long k = b * ns / gs; k < (b + 1) * ns / gs; ++k) {
                 items.push_back(slab[k]);
