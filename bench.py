@@ -68,16 +68,19 @@ def parse():
     return ap.parse_args()
 
 
-def replicas(islf):
+def replicas(islf, n=None):
+    """One replica per temperature; n > 3 cycles through the temperatures
+    (larger-than-cache batches)."""
     Lx, Ly, Lz = SHAPE
-    return [islf.Replica(Lx, Ly, Lz, islf.GAPBC, J=1.0, beta=1.0 / T, H=0.0, h1=H1, hn=-H1, seed=SEED + i,
-                         replica=i, init=islf.INIT_RANDOM) for i, T in enumerate(TEMPS)]
+    n = len(TEMPS) if n is None else n
+    return [islf.Replica(Lx, Ly, Lz, islf.GAPBC, J=1.0, beta=1.0 / TEMPS[i % len(TEMPS)], H=0.0, h1=H1, hn=-H1,
+                         seed=SEED + i, replica=i, init=islf.INIT_RANDOM) for i in range(n)]
 
 
-def run_form(islf, torch, form, fmt, steps, warmup, chunk, timings=False):
+def run_form(islf, torch, form, fmt, steps, warmup, chunk, timings=False, n_reps=None):
     mode = {"persistent": islf.EXEC_PERSISTENT, "batched": islf.EXEC_BATCHED, "plain": islf.EXEC_PLAIN}[form]
     f = {"int8": islf.INT8, "bitpack": islf.BITPACK}[fmt]
-    reps = replicas(islf)
+    reps = replicas(islf, n_reps)
     ctx = islf.Context(reps, spin_format=f, obs_capacity=steps + warmup + 64, exec_mode=mode)
     try:
         chunk = max(1, min(chunk, steps))
@@ -226,6 +229,10 @@ def main():
             r = run_form(islf, torch, form, fmt, min(args.steps, 100), 5, min(args.chunk, 50))
             forms[f"{form}_{fmt}"] = round(updates_per_sweep / (r["ms_per_sweep"] * 1e6), 2)
             print(f"# {form}/{fmt}: {r}", file=sys.stderr, flush=True)
+        # a batch larger than the 256 MB last-level cache: 8 int8 replicas, 369 MB of spins
+        r = run_form(islf, torch, "batched", "int8", min(args.steps, 50), 5, min(args.chunk, 50), n_reps=8)
+        forms["batched_int8_8x46M_369MB"] = round(8 * N / (r["ms_per_sweep"] * 1e6), 2)
+        print(f"# batched/int8 x8: {r}", file=sys.stderr, flush=True)
 
     # dominant kernel: the sweep kernel.  Its A and B launches of one sweep
     # together update every site of every replica once (A: phase 0 and the
