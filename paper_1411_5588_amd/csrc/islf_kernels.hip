@@ -544,18 +544,21 @@ __device__ __forceinline__ uint32_t bp_flips_pairs(uint32_t S, uint32_t b2, uint
     transpose8x8(w[0], w[1]);
     transpose8x8(w[2], w[3]);
     uint32_t F = 0;
-    // w[0] always holds the current iteration's pair indices
+    // w[0] always holds the current iteration's pair indices; the thresholds
+    // are read before the draws so that the LDS latency overlaps Philox
 #pragma unroll
     for (int g = 0; g < 4; ++g) {
+        uint2 t[4];
+#pragma unroll
+        for (int l = 0; l < 4; ++l) t[l] = tb->pair[(w[0] >> (8 * l)) & 0xFFu];
         uint32_t r0[4], r1[4];
         philox10(gq + 2u * (uint32_t)g, v.t, v.replica, 0u, v.key0, v.key1, r0);
         philox10(gq + 2u * (uint32_t)(g + 4), v.t, v.replica, 0u, v.key0, v.key1, r1);
         uint32_t Fg = 0;
 #pragma unroll
         for (int l = 0; l < 4; ++l) {
-            const uint2 t = tb->pair[(w[0] >> (8 * l)) & 0xFFu];
-            Fg |= (r0[l] <= t.x ? 1u : 0u) << l;
-            Fg |= (r1[l] <= t.y ? 1u : 0u) << (l + 16);
+            Fg |= (r0[l] <= t[l].x ? 1u : 0u) << l;
+            Fg |= (r1[l] <= t[l].y ? 1u : 0u) << (l + 16);
         }
         F |= Fg << (4 * g);
         w[0] = w[1];
