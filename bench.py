@@ -12,9 +12,17 @@ timing starts; nothing is copied to the host inside the timed region.
 Prints one JSON line.  Besides the headline (bit-packed spins, batched form)
 it reports the int8 format and the plain one-lattice-per-launch and
 persistent forms on the same workload, the roofline of the dominant kernel
-(the sweep kernel: its A and B launches, timed live with HIP events on the
-context's stream) and the CPU oracle timed on a bounded sample of the same
+(the sweep kernel) and the CPU oracle timed on a bounded sample of the same
 workload.
+
+The batched form deals the replicas into concurrent groups, each sweeping on
+its own stream, so the sweep kernel's launches of one kind (A or B) run as a
+wave of concurrent dispatches that together update half a sweep of every
+replica.  The roofline's unit is that launch wave: its algorithmic operations
+over its average duration, i.e. the timed region (HIP events on the
+context's stream, which forks to and joins from the group streams) divided by
+the waves in it.  The per-launch time of a single launch chain over all
+replicas (HIP events around each launch) is reported beside it.
 """
 from __future__ import annotations
 
@@ -53,8 +61,10 @@ def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=400)
-    ap.add_argument("--warmup", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=50)
     ap.add_argument("--chunk", type=int, default=50, help="sweeps per captured graph launch")
+    ap.add_argument("--groups", type=int, default=0,
+                    help="concurrent replica groups of the batched form (0: automatic, 1: one launch chain)")
     ap.add_argument("--form", choices=["persistent", "batched", "plain"], default="batched")
     ap.add_argument("--fmt", choices=["int8", "bitpack"], default="bitpack")
     ap.add_argument("--no-extras", action="store_true", help="skip the other forms and formats")
@@ -77,16 +87,22 @@ def replicas(islf, n=None):
                          seed=SEED + i, replica=i, init=islf.INIT_RANDOM) for i in range(n)]
 
 
-def run_form(islf, torch, form, fmt, steps, warmup, chunk, timings=False, n_reps=None):
+def run_form(islf, torch, form, fmt, steps, warmup, chunk, timings=False, n_reps=None, groups=0):
     mode = {"persistent": islf.EXEC_PERSISTENT, "batched": islf.EXEC_BATCHED, "plain": islf.EXEC_PLAIN}[form]
     f = {"int8": islf.INT8, "bitpack": islf.BITPACK}[fmt]
     reps = replicas(islf, n_reps)
     ctx = islf.Context(reps, spin_format=f, obs_capacity=steps + warmup + 64, exec_mode=mode)
     try:
         chunk = max(1, min(chunk, steps))
-        if warmup:
-            ctx.sweep(warmup)
+        if groups:
+            ctx.set_groups(groups)
         ctx.capture(chunk)
+        # warm-up: replays of the same graph (its first launch is slower), then
+        # eager sweeps for the remainder
+        if warmup // chunk:
+            ctx.replay(warmup // chunk)
+        if warmup % chunk:
+            ctx.sweep(warmup % chunk)
         n_launch = steps // chunk
         rest = steps - n_launch * chunk
         s = ctx.stream
@@ -103,10 +119,13 @@ def run_form(islf, torch, form, fmt, steps, warmup, chunk, timings=False, n_reps
         total_ms = t0.elapsed_time(t1)
         for i in range(len(reps)):
             assert ctx.sweep_count(i) == warmup + steps
-        out = dict(ms_per_sweep=total_ms / steps, sweeps_per_launch=chunk, launches=n_launch)
+        out = dict(ms_per_sweep=total_ms / steps, sweeps_per_launch=chunk, launches=n_launch,
+                   groups=ctx.get_groups() if form == "batched" else 1, grid=ctx.get_grid())
         if timings:
+            # per-launch times of one launch chain over all replicas
+            ctx.set_groups(1)
             ms, cnt = ctx.phase_timings(8)
-            out["kernel_ms"] = {"A": float(ms[0]), "B": float(ms[1]), "close": float(ms[2])}
+            out["kernel_ms"] = {"A": float(ms[0]), "B": float(ms[1]), "close": float(ms[2]), "grid": ctx.get_grid()}
             out["kernel_launches"] = [int(c) for c in cnt]
         return out
     finally:
@@ -145,9 +164,9 @@ def kernel_source_hash():
 
 
 def committed_traffic(fmt):
-    """HBM bytes per sweep-kernel dispatch (mean of the A and B launches) from
-    the committed counter summary, or None when the kernel source has changed
-    since it was taken."""
+    """HBM bytes per launch wave of the sweep kernel (the A or B dispatches of
+    all groups, half a sweep of every replica) from the committed counter
+    summary, or None when the kernel source has changed since it was taken."""
     try:
         text = open(PROFILE_TRAFFIC).read()
     except OSError:
@@ -155,7 +174,7 @@ def committed_traffic(fmt):
     m = re.search(r"kernel_source_sha256_16:\s*([0-9a-f]+)", text)
     if not m or m.group(1) != kernel_source_hash():
         return None
-    m = re.search(rf"traffic_bytes_per_dispatch\[{fmt}\]:\s*([0-9.eE+]+)", text)
+    m = re.search(rf"traffic_bytes_per_wave\[{fmt}\]:\s*([0-9.eE+]+)", text)
     return float(m.group(1)) if m else None
 
 
@@ -177,7 +196,7 @@ def main():
     args = parse()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (asked for --gpus {args.gpus}): the sweep path runs on a "
-              f"single GPU and sharding across GPUs is not part of this build", file=sys.stderr)
+              f"single GPU and sharding across GPUs is not implemented", file=sys.stderr)
         sys.exit(2)
     import torch
 
@@ -217,7 +236,8 @@ def main():
     n_reps = len(TEMPS)
     updates_per_sweep = N * n_reps
 
-    main_run = run_form(islf, torch, args.form, args.fmt, args.steps, args.warmup, args.chunk, timings=True)
+    main_run = run_form(islf, torch, args.form, args.fmt, args.steps, args.warmup, args.chunk, timings=True,
+                        groups=args.groups)
     print(f"# {args.form}/{args.fmt}: {main_run}", file=sys.stderr, flush=True)
     value = updates_per_sweep / (main_run["ms_per_sweep"] * 1e6)
 
@@ -226,29 +246,40 @@ def main():
         for form, fmt in (("plain", "bitpack"), ("batched", "int8"), ("plain", "int8"), ("persistent", "bitpack")):
             if (form, fmt) == (args.form, args.fmt):
                 continue
-            r = run_form(islf, torch, form, fmt, min(args.steps, 100), 5, min(args.chunk, 50))
+            r = run_form(islf, torch, form, fmt, min(args.steps, 100), min(args.chunk, 50), min(args.chunk, 50))
             forms[f"{form}_{fmt}"] = round(updates_per_sweep / (r["ms_per_sweep"] * 1e6), 2)
             print(f"# {form}/{fmt}: {r}", file=sys.stderr, flush=True)
         # a batch larger than the 256 MB last-level cache: 8 int8 replicas, 369 MB of spins
-        r = run_form(islf, torch, "batched", "int8", min(args.steps, 50), 5, min(args.chunk, 50), n_reps=8)
+        r = run_form(islf, torch, "batched", "int8", min(args.steps, 50), min(args.chunk, 50), min(args.chunk, 50),
+                     n_reps=8)
         forms["batched_int8_8x46M_369MB"] = round(8 * N / (r["ms_per_sweep"] * 1e6), 2)
         print(f"# batched/int8 x8: {r}", file=sys.stderr, flush=True)
 
     # dominant kernel: the sweep kernel.  Its A and B launches of one sweep
     # together update every site of every replica once (A: phase 0 and the
-    # previous sweep's phase 3, B: phases 1 and 2), so a launch updates half
-    # a sweep on average; the per-launch time is the mean of the A and B times
+    # previous sweep's phase 3, B: phases 1 and 2), so a launch wave (the A or
+    # B dispatches of all concurrent groups) updates half a sweep of every
+    # replica; its average duration is the timed region over its 2 x steps
+    # waves (the region also holds one closing launch and fold per graph
+    # launch, so this slightly overstates the wave time)
+    updates_per_wave = n_reps * N / 2
+    wave_ms = main_run["ms_per_sweep"] / 2
+    achieved_tops = OPS_PER_UPDATE * updates_per_wave / (wave_ms * 1e-3) / 1e12
+    # one launch chain over all replicas, HIP events around each launch
     kms = main_run["kernel_ms"]
-    main_ms = 0.5 * (kms["A"] + kms["B"])
-    updates_per_launch = n_reps * N / 2
-    achieved_tops = OPS_PER_UPDATE * updates_per_launch / (main_ms * 1e-3) / 1e12
+    chain_ms = 0.5 * (kms["A"] + kms["B"])
+    chain_tops = OPS_PER_UPDATE * updates_per_wave / (chain_ms * 1e-3) / 1e12
     traffic = committed_traffic(args.fmt)
     roofline = {"bound": "alu", "achieved": round(achieved_tops, 2), "peak": round(VALU_PEAK_TOPS, 1),
                 "unit": "T int-op/s", "frac": round(achieved_tops / VALU_PEAK_TOPS, 4), "traffic": traffic,
-                "kernel": "k_sweep (A and B launches)", "kernel_ms": round(main_ms, 5),
-                "ops_per_update": OPS_PER_UPDATE,
-                "hbm_view": {"algorithmic_GBs": round(BYTES_PER_UPDATE[args.fmt] * updates_per_launch
-                                                      / (main_ms * 1e-3) / 1e9, 1),
+                "kernel": "k_sweep (A and B launches)",
+                "launch_unit": f"wave of {main_run['groups']} concurrent group dispatches of "
+                               f"{main_run['grid']} workgroups, half a sweep of every replica",
+                "wave_ms": round(wave_ms, 5), "ops_per_update": OPS_PER_UPDATE,
+                "single_chain": {"kernel_ms": round(chain_ms, 5), "workgroups": kms.get("grid"),
+                                 "achieved": round(chain_tops, 2), "frac": round(chain_tops / VALU_PEAK_TOPS, 4)},
+                "hbm_view": {"algorithmic_GBs": round(BYTES_PER_UPDATE[args.fmt] * updates_per_wave
+                                                      / (wave_ms * 1e-3) / 1e9, 1),
                              "peak_GBs": HBM_PEAK_GBS}}
 
     prof = layer_profile_rate(islf, torch)
@@ -263,7 +294,8 @@ def main():
         "config": {"workload": f"thin film {Lx}x{Ly}x{Lz} GAPBC, h1=+{H1}/hn=-{H1}, one replica per T in "
                                f"{list(TEMPS)}, {args.fmt} spins, {args.form} form, "
                                f"{main_run['sweeps_per_launch']} sweeps per graph launch",
-                   "sites_per_replica": N, "replicas": n_reps, "form": args.form, "spin_format": args.fmt},
+                   "sites_per_replica": N, "replicas": n_reps, "form": args.form, "spin_format": args.fmt,
+                   "groups": main_run["groups"], "workgroups_per_launch": main_run["grid"]},
         "forms": forms,
         "roofline": roofline,
         "layer_profile": prof,

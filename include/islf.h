@@ -213,9 +213,14 @@ islf_status islf_batch_add(islf_ctx *ctx, const islf_replica_desc *desc, int32_t
 islf_status islf_batch_retire(islf_ctx *ctx, int32_t slot);
 
 /* Records k_sweeps sweeps of the current batch (in the current execution
- * form) as a HIP graph; islf_run_graph replays it n_replays times on the
- * context's stream.  Admitting or retiring a replica invalidates the graph
- * (run_graph then returns ESTATE until the next capture). */
+ * form) as HIP graphs: one graph, or with concurrent replica groups
+ * (islf_set_groups) one graph per group captured on the group's stream.
+ * islf_run_graph replays them n_replays times, ordered after the work issued
+ * before on the context's stream and before the work issued after it there
+ * (the group streams fork from and join back to it).  Admitting or retiring
+ * a replica, or changing the groups or the grid, invalidates the graphs
+ * (run_graph then returns ESTATE until the next capture).  Errors: EINVAL,
+ * ESTATE, EDEVICE. */
 islf_status islf_graph_capture(islf_ctx *ctx, uint32_t k_sweeps);
 islf_status islf_run_graph(islf_ctx *ctx, uint32_t n_replays);
 
@@ -246,11 +251,27 @@ islf_status islf_autotune(islf_ctx *ctx, uint32_t sweeps);
 islf_status islf_layer_profile(islf_ctx *ctx, int32_t rep, int32_t *dev_out);
 islf_status islf_layer_profile_add(islf_ctx *ctx, int32_t rep, int64_t *dev_acc);
 
+/* Concurrent replica groups of the batched form.  The live replicas are dealt
+ * into this many groups of about equal site counts; each group sweeps on its
+ * own stream (group 0 on the context's stream, the others on streams the
+ * context owns, forked from and joined back to the context's stream, also
+ * inside a captured graph), so that the tail of one group's launch overlaps
+ * the launches of the others.  Replicas are independent, so the results are
+ * the same for every choice.  0 (the default) means min(4, live replicas);
+ * 1 gives one launch chain over all replicas.  Changing it invalidates a
+ * captured graph.  Errors: EINVAL (NULL context, groups < 0 or > 16). */
+islf_status islf_set_groups(islf_ctx *ctx, int32_t groups);
+islf_status islf_get_groups(const islf_ctx *ctx, int32_t *groups);
+
 /* Workgroups per A / B launch of the batched and plain forms; the work of a
  * launch is split evenly over them.  0 (the default) means two per resident
- * slot of the sweep kernels on the device; islf_get_grid reports the value in
- * use.  Every choice computes the same result.  Changing it invalidates a
- * captured graph.  Errors: EINVAL (NULL context, workgroups < 0 or > 2^20). */
+ * slot of the sweep kernels on the device, divided among the concurrent
+ * replica groups of the batched form (at least 64 per group); a nonzero value
+ * applies to every group's launches.  islf_get_grid reports the count of one
+ * launch of the context's form (of one group's launch with several groups;
+ * of the batched form for a persistent context).  Every choice computes the
+ * same result.  Changing it invalidates a captured graph.  Errors: EINVAL
+ * (NULL context, workgroups < 0 or > 2^20). */
 islf_status islf_set_grid(islf_ctx *ctx, int32_t workgroups);
 islf_status islf_get_grid(const islf_ctx *ctx, int32_t *workgroups);
 

@@ -198,6 +198,7 @@ struct islf_ctx {
     void *user = nullptr;
     int exec = ISLF_EXEC_BATCHED;
     int num_cu = 0;
+    int resident_slots = 0;    // workgroups of the sweep kernels resident at once on the device
     int sweep_slots = 0;       // default workgroups per sweep launch (2 per resident slot)
     int grid_override = 0;     // workgroups per batched / plain launch (0: sweep_slots)
     int persistent_grid = 0;   // co-resident blocks of the persistent kernel
@@ -212,11 +213,23 @@ struct islf_ctx {
     int live_capacity = 0;
     Plan batched, persistent;
     std::vector<Plan> plain;                    // per slot
+    // batched form with concurrent replica groups: group g sweeps its
+    // replicas on its own stream (g = 0: the context's stream)
+    int groups_req = 0;                         // 0: automatic
+    bool groups_valid = false;
+    std::vector<Plan> group_plan;
+    std::vector<int> group_off, group_len;      // into d_group_live
+    int *d_group_live = nullptr;
+    int group_live_cap = 0;
+    std::vector<hipStream_t> side_stream;       // groups 1 ..
+    std::vector<hipEvent_t> side_event;         // [0] fork, [g] join of group g
     std::vector<int> live;
     bool dirty = true;
 
-    hipGraph_t graph = nullptr;
-    hipGraphExec_t graph_exec = nullptr;
+    // captured sweeps: one single-stream graph per concurrent group (one
+    // graph otherwise), replayed on the group's stream
+    std::vector<hipGraph_t> graphs;
+    std::vector<hipGraphExec_t> graph_execs;
     uint32_t graph_sweeps = 0;
     bool graph_valid = false;
 };
@@ -393,6 +406,8 @@ static void free_plan(islf_ctx *c, Plan &p)
 }
 
 constexpr double kTailTaper = 0.2;
+constexpr int kAutoGroups = 4;
+constexpr int kMaxStreamGroups = 16;   // concurrent replica groups of the batched form (hardware queues per process)
 
 // Splits the work into about `grid` runs of equal cost, one per workgroup:
 // workgroup b gets items [first[b], first[b+1]).  The slab items are spread
@@ -426,8 +441,18 @@ static int partition_items(const std::vector<Entry> &slab, const std::vector<Ent
     // get smaller shares, weight 1 + a (1 - 2 u) at u = (d + 0.5) / grid
     const double a = kTailTaper;
     std::vector<double> cum(grid + 1, 0.0);
+    const long q = grid / 8, r8 = grid % 8;
     for (int r = 0; r < grid; ++r) {
-        const long d = (grid % 8) ? r : (long)(r % (grid / 8)) * 8 + r / (grid / 8);
+        // the kernel gives XCD x (blocks x, x+8, ...) the runs from x*q + min(x, r8)
+        long x, k;
+        if (r < r8 * (q + 1)) {
+            x = r / (q + 1);
+            k = r % (q + 1);
+        } else {
+            x = r8 + (r - r8 * (q + 1)) / q;
+            k = (r - r8 * (q + 1)) % q;
+        }
+        const long d = x + 8 * k;
         const double u = (d + 0.5) / grid;
         cum[r + 1] = cum[r] + 1.0 + a * (1.0 - 2.0 * u);
     }
@@ -509,12 +534,97 @@ static islf_status sync_tables(islf_ctx *c)
     c->batched.valid = false;
     c->persistent.valid = false;
     for (Plan &p : c->plain) p.valid = false;
+    c->groups_valid = false;
     c->dirty = false;
     c->graph_valid = false;
     return ISLF_OK;
 }
 
 // The plans the context's execution form launches, built if needed.
+static int num_groups(const islf_ctx *c)
+{
+    const int nl = (int)c->live.size();
+    const int want = c->groups_req ? c->groups_req : kAutoGroups;
+    return std::max(1, std::min(want, nl));
+}
+
+// Workgroups per A / B launch of a form: the override, else two per resident
+// slot, divided among the concurrent groups of the batched form (the groups
+// together keep about two workgroups per slot in flight).
+static int launch_grid(const islf_ctx *c, int exec)
+{
+    if (c->grid_override) return c->grid_override;
+    const int G = exec == ISLF_EXEC_BATCHED ? num_groups(c) : 1;
+    return G > 1 ? std::max(64, (c->sweep_slots + G / 2) / G) : c->sweep_slots;
+}
+
+// Concurrent groups of the batched form: live replicas dealt to the group
+// with the fewest sites so far (largest first), one launch plan per group
+// (2 x resident slots / groups workgroups, so that all groups together keep
+// about two per slot in flight and each group's tail is filled by the
+// others' launches), the groups' live lists on the device, and the side
+// streams and events.
+static islf_status prepare_groups(islf_ctx *c)
+{
+    islf_status st = sync_tables(c);
+    if (st != ISLF_OK) return st;
+    if (c->groups_valid) return ISLF_OK;
+    const int G = num_groups(c);
+    std::vector<int> order(c->live);
+    auto sites = [&](int r) {
+        const islf_replica_desc &d = c->reps[r].desc;
+        return (long long)d.Lx * d.Ly * d.Lz;
+    };
+    std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return sites(a) > sites(b); });
+    std::vector<std::vector<int>> grp(G);
+    std::vector<long long> load(G, 0);
+    for (int r : order) {
+        const int g = (int)(std::min_element(load.begin(), load.end()) - load.begin());
+        grp[g].push_back(r);
+        load[g] += sites(r);
+    }
+    std::vector<int> flat;
+    c->group_off.assign(G, 0);
+    c->group_len.assign(G, 0);
+    for (int g = 0; g < G; ++g) {
+        std::sort(grp[g].begin(), grp[g].end());
+        c->group_off[g] = (int)flat.size();
+        c->group_len[g] = (int)grp[g].size();
+        flat.insert(flat.end(), grp[g].begin(), grp[g].end());
+    }
+    if ((int)flat.size() > c->group_live_cap) {
+        dev_free(c, c->d_group_live);
+        c->group_live_cap = std::max<int>((int)flat.size(), 2 * c->group_live_cap);
+        c->d_group_live = (int *)dev_alloc(c, sizeof(int) * c->group_live_cap);
+        if (!c->d_group_live) return fail(ISLF_ENOMEM, "cannot allocate group lists");
+    }
+    if (!flat.empty())
+        HIP_TRY(hipMemcpyAsync(c->d_group_live, flat.data(), sizeof(int) * flat.size(), hipMemcpyHostToDevice,
+                               c->stream));
+    if ((int)c->group_plan.size() < G) c->group_plan.resize(G);
+    for (int g = 0; g < G; ++g) {
+        std::vector<Entry> S, M;
+        for (int r : grp[g]) {
+            S.insert(S.end(), c->reps[r].slab.begin(), c->reps[r].slab.end());
+            M.insert(M.end(), c->reps[r].main.begin(), c->reps[r].main.end());
+        }
+        st = build_plan(c, c->group_plan[g], S, M, launch_grid(c, ISLF_EXEC_BATCHED));
+        if (st != ISLF_OK) return st;
+    }
+    while ((int)c->side_stream.size() < G - 1) {
+        hipStream_t sst = nullptr;
+        HIP_TRY(hipStreamCreateWithFlags(&sst, hipStreamNonBlocking));
+        c->side_stream.push_back(sst);
+    }
+    while ((int)c->side_event.size() < G) {
+        hipEvent_t ev = nullptr;
+        HIP_TRY(hipEventCreateWithFlags(&ev, hipEventDisableTiming));
+        c->side_event.push_back(ev);
+    }
+    c->groups_valid = true;
+    return ISLF_OK;
+}
+
 static islf_status prepare_plans(islf_ctx *c, int exec)
 {
     islf_status st = sync_tables(c);
@@ -526,6 +636,7 @@ static islf_status prepare_plans(islf_ctx *c, int exec)
         }
     };
     if (c->live.empty()) return ISLF_OK;
+    if (exec == ISLF_EXEC_BATCHED && num_groups(c) > 1) return prepare_groups(c);
     if (exec == ISLF_EXEC_BATCHED && !c->batched.valid) {
         std::vector<Entry> S, M;
         lists(c->live, S, M);
@@ -609,12 +720,20 @@ static islf_status add_replica(islf_ctx *c, const islf_replica_desc *desc, int *
     return ISLF_OK;
 }
 
+static void destroy_graphs(islf_ctx *c)
+{
+    for (hipGraphExec_t ex : c->graph_execs) (void)hipGraphExecDestroy(ex);
+    for (hipGraph_t g : c->graphs) (void)hipGraphDestroy(g);
+    c->graph_execs.clear();
+    c->graphs.clear();
+    c->graph_valid = false;
+}
+
 static void destroy_ctx(islf_ctx *c)
 {
     if (!c) return;
-    if (c->stream || true) (void)hipStreamSynchronize(c->stream);
-    if (c->graph_exec) (void)hipGraphExecDestroy(c->graph_exec);
-    if (c->graph) (void)hipGraphDestroy(c->graph);
+    (void)hipStreamSynchronize(c->stream);
+    destroy_graphs(c);
     for (auto &R : c->reps) dev_free(c, R.mem);
     dev_free(c, c->d_desc);
     dev_free(c, c->d_state);
@@ -624,6 +743,10 @@ static void destroy_ctx(islf_ctx *c)
     free_plan(c, c->batched);
     free_plan(c, c->persistent);
     for (Plan &p : c->plain) free_plan(c, p);
+    for (Plan &p : c->group_plan) free_plan(c, p);
+    dev_free(c, c->d_group_live);
+    for (hipStream_t sst : c->side_stream) (void)hipStreamDestroy(sst);
+    for (hipEvent_t ev : c->side_event) (void)hipEventDestroy(ev);
     delete c;
 }
 
@@ -664,7 +787,8 @@ extern "C" islf_status islf_create_with_allocator(const islf_replica_desc *reps,
     if (sweep_blocks_per_cu(spin_format, &per_cu_sweep) != hipSuccess || per_cu_sweep < 1) per_cu_sweep = 1;
     // two workgroups per resident slot: measured faster than one (a single
     // round leaves slots idle while the last workgroups finish)
-    c->sweep_slots = 2 * c->num_cu * per_cu_sweep;
+    c->resident_slots = c->num_cu * per_cu_sweep;
+    c->sweep_slots = 2 * c->resident_slots;
     int per_cu = 0;
     if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, persistent_kernel(spin_format), kBlock, 0) != hipSuccess ||
         per_cu < 1)
@@ -792,35 +916,67 @@ extern "C" islf_status islf_set_exec(islf_ctx *ctx, int32_t mode)
 // events bracket each launch (A and B of sweep s at ev[4s..4s+3], F + fold
 // at ev[4n], ev[4n+1]).
 static hipError_t enqueue_plan(islf_ctx *c, const Plan &p, const int *dl, int nl, uint32_t n,
-                               hipEvent_t *ev = nullptr)
+                               hipEvent_t *ev = nullptr, hipStream_t strm = nullptr)
 {
+    if (!strm) strm = c->stream;
     hipError_t e = hipSuccess;
     auto mark = [&](size_t i) {
-        if (ev && e == hipSuccess) e = hipEventRecord(ev[i], c->stream);
+        if (ev && e == hipSuccess) e = hipEventRecord(ev[i], strm);
     };
     for (uint32_t s = 0; s < n && e == hipSuccess; ++s) {
         mark(4 * (size_t)s);
         if (e == hipSuccess)
             e = launch_sweep(c->fmt, KIND_A, c->d_desc, c->d_state, p.items, p.first, p.grid, dl, nl, s,
-                             s ? FLAG_PREV : 0u, c->stream);
+                             s ? FLAG_PREV : 0u, strm);
         mark(4 * (size_t)s + 1);
         mark(4 * (size_t)s + 2);
         if (e == hipSuccess)
             e = launch_sweep(c->fmt, KIND_B, c->d_desc, c->d_state, p.items, p.first, p.grid, dl, nl, s,
-                             s ? FLAG_FOLD : 0u, c->stream);
+                             s ? FLAG_FOLD : 0u, strm);
         mark(4 * (size_t)s + 3);
     }
     mark(4 * (size_t)n);
     if (e == hipSuccess)
         e = launch_sweep(c->fmt, KIND_F, c->d_desc, c->d_state, p.items, p.first, p.slab_grid, dl, nl, n - 1, 0u,
-                         c->stream);
-    if (e == hipSuccess) e = launch_fold(c->d_desc, c->d_state, dl, nl, n - 1, n, c->stream);
+                         strm);
+    if (e == hipSuccess) e = launch_fold(c->d_desc, c->d_state, dl, nl, n - 1, n, strm);
     mark(4 * (size_t)n + 1);
     return e;
 }
 
 // Enqueues n sweeps in the context's execution form (plans prepared, no
 // checks, no sync).
+// Concurrent groups: group g issues on group_stream(g).  Fork: every side
+// stream waits for the work issued before on the context's stream; join: the
+// context's stream waits for every side stream.
+static hipStream_t group_stream(const islf_ctx *c, int g)
+{
+    return g ? c->side_stream[g - 1] : c->stream;
+}
+
+static hipError_t fork_groups(islf_ctx *c, int G)
+{
+    hipError_t e = hipEventRecord(c->side_event[0], c->stream);
+    for (int g = 1; g < G && e == hipSuccess; ++g) e = hipStreamWaitEvent(c->side_stream[g - 1], c->side_event[0], 0);
+    return e;
+}
+
+static hipError_t join_groups(islf_ctx *c, int G)
+{
+    hipError_t e = hipSuccess;
+    for (int g = 1; g < G && e == hipSuccess; ++g) {
+        e = hipEventRecord(c->side_event[g], c->side_stream[g - 1]);
+        if (e == hipSuccess) e = hipStreamWaitEvent(c->stream, c->side_event[g], 0);
+    }
+    return e;
+}
+
+static hipError_t enqueue_group(islf_ctx *c, int g, uint32_t n)
+{
+    return enqueue_plan(c, c->group_plan[g], c->d_group_live + c->group_off[g], c->group_len[g], n, nullptr,
+                        group_stream(c, g));
+}
+
 static islf_status enqueue_sweeps(islf_ctx *c, uint32_t n)
 {
     const int nl = (int)c->live.size();
@@ -830,6 +986,13 @@ static islf_status enqueue_sweeps(islf_ctx *c, uint32_t n)
         hipError_t e = launch_persistent(c->fmt, c->d_desc, c->d_state, p.items, p.first, c->d_live, nl, n,
                                          c->d_sync, p.grid, c->stream);
         if (e != hipSuccess) return fail(ISLF_EDEVICE, "persistent launch failed: %s", hipGetErrorString(e));
+        return ISLF_OK;
+    }
+    if (c->exec == ISLF_EXEC_BATCHED && num_groups(c) > 1) {
+        const int G = num_groups(c);
+        HIP_TRY(fork_groups(c, G));
+        for (int g = 0; g < G; ++g) HIP_TRY(enqueue_group(c, g, n));
+        HIP_TRY(join_groups(c, G));
         return ISLF_OK;
     }
     if (c->exec == ISLF_EXEC_BATCHED) {
@@ -1063,26 +1226,39 @@ extern "C" islf_status islf_graph_capture(islf_ctx *ctx, uint32_t k_sweeps)
     if (!ctx->stream) return fail(ISLF_ESTATE, "graph capture needs a non-default stream");
     islf_status st = prepare_plans(ctx, ctx->exec);
     if (st != ISLF_OK) return st;
-    if (ctx->graph_exec) {
-        (void)hipGraphExecDestroy(ctx->graph_exec);
-        ctx->graph_exec = nullptr;
+    destroy_graphs(ctx);
+    // concurrent groups: one graph per group, captured on the group's own
+    // stream, so that replays run each group on a stream the context owns
+    // (the streams a runtime picks for the branches of one multi-stream graph
+    // may share a hardware queue and serialise the groups)
+    const bool grouped = ctx->exec == ISLF_EXEC_BATCHED && num_groups(ctx) > 1;
+    const int G = grouped ? num_groups(ctx) : 1;
+    for (int gi = 0; gi < G; ++gi) {
+        hipStream_t sg = group_stream(ctx, gi);
+        HIP_TRY(hipStreamBeginCapture(sg, hipStreamCaptureModeThreadLocal));
+        hipError_t ee = hipSuccess;
+        if (grouped) ee = enqueue_group(ctx, gi, k_sweeps);
+        else st = enqueue_sweeps(ctx, k_sweeps);
+        hipGraph_t g = nullptr;
+        hipError_t e = hipStreamEndCapture(sg, &g);
+        if (st != ISLF_OK || ee != hipSuccess) {
+            if (g) (void)hipGraphDestroy(g);
+            destroy_graphs(ctx);
+            return st != ISLF_OK ? st : fail(ISLF_EDEVICE, "launch during capture failed: %s", hipGetErrorString(ee));
+        }
+        if (e != hipSuccess) {
+            destroy_graphs(ctx);
+            return fail(ISLF_EDEVICE, "graph capture failed: %s", hipGetErrorString(e));
+        }
+        ctx->graphs.push_back(g);
+        hipGraphExec_t ex = nullptr;
+        e = hipGraphInstantiate(&ex, g, nullptr, nullptr, 0);
+        if (e != hipSuccess) {
+            destroy_graphs(ctx);
+            return fail(ISLF_EDEVICE, "graph instantiation failed: %s", hipGetErrorString(e));
+        }
+        ctx->graph_execs.push_back(ex);
     }
-    if (ctx->graph) {
-        (void)hipGraphDestroy(ctx->graph);
-        ctx->graph = nullptr;
-    }
-    ctx->graph_valid = false;
-    HIP_TRY(hipStreamBeginCapture(ctx->stream, hipStreamCaptureModeThreadLocal));
-    st = enqueue_sweeps(ctx, k_sweeps);
-    hipGraph_t g = nullptr;
-    hipError_t e = hipStreamEndCapture(ctx->stream, &g);
-    if (st != ISLF_OK) {
-        if (g) (void)hipGraphDestroy(g);
-        return st;
-    }
-    if (e != hipSuccess) return fail(ISLF_EDEVICE, "graph capture failed: %s", hipGetErrorString(e));
-    ctx->graph = g;
-    HIP_TRY(hipGraphInstantiate(&ctx->graph_exec, g, nullptr, nullptr, 0));
     ctx->graph_sweeps = k_sweeps;
     ctx->graph_valid = true;
     return ISLF_OK;
@@ -1094,7 +1270,11 @@ extern "C" islf_status islf_run_graph(islf_ctx *ctx, uint32_t n_replays)
     if (!ctx->graph_valid || ctx->dirty) return fail(ISLF_ESTATE, "no valid captured graph");
     islf_status st = check_sweep_range(ctx, (uint64_t)ctx->graph_sweeps * n_replays);
     if (st != ISLF_OK) return st;
-    for (uint32_t i = 0; i < n_replays; ++i) HIP_TRY(hipGraphLaunch(ctx->graph_exec, ctx->stream));
+    const int G = (int)ctx->graph_execs.size();
+    if (G > 1) HIP_TRY(fork_groups(ctx, G));
+    for (uint32_t i = 0; i < n_replays; ++i)
+        for (int g = 0; g < G; ++g) HIP_TRY(hipGraphLaunch(ctx->graph_execs[g], group_stream(ctx, g)));
+    if (G > 1) HIP_TRY(join_groups(ctx, G));
     for (int r : ctx->live) ctx->reps[r].t_host += (uint64_t)ctx->graph_sweeps * n_replays;
     return ISLF_OK;
 }
@@ -1288,15 +1468,33 @@ extern "C" islf_status islf_set_grid(islf_ctx *ctx, int32_t workgroups)
     if (workgroups < 0 || workgroups > (1 << 20)) return fail(ISLF_EINVAL, "invalid workgroup count %d", workgroups);
     ctx->grid_override = workgroups;
     ctx->batched.valid = false;
+    ctx->groups_valid = false;
     for (Plan &p : ctx->plain) p.valid = false;
     ctx->graph_valid = false;
+    return ISLF_OK;
+}
+
+extern "C" islf_status islf_set_groups(islf_ctx *ctx, int32_t groups)
+{
+    if (!ctx) return fail(ISLF_EINVAL, "NULL context");
+    if (groups < 0 || groups > kMaxStreamGroups) return fail(ISLF_EINVAL, "invalid group count %d", groups);
+    ctx->groups_req = groups;
+    ctx->groups_valid = false;
+    ctx->graph_valid = false;
+    return ISLF_OK;
+}
+
+extern "C" islf_status islf_get_groups(const islf_ctx *ctx, int32_t *groups)
+{
+    if (!ctx || !groups) return fail(ISLF_EINVAL, "NULL argument");
+    *groups = num_groups(ctx);
     return ISLF_OK;
 }
 
 extern "C" islf_status islf_get_grid(const islf_ctx *ctx, int32_t *workgroups)
 {
     if (!ctx || !workgroups) return fail(ISLF_EINVAL, "NULL argument");
-    *workgroups = ctx->grid_override ? ctx->grid_override : ctx->sweep_slots;
+    *workgroups = launch_grid(ctx, ctx->exec == ISLF_EXEC_PERSISTENT ? ISLF_EXEC_BATCHED : ctx->exec);
     return ISLF_OK;
 }
 
@@ -1304,7 +1502,15 @@ extern "C" islf_status islf_phase_timings(islf_ctx *ctx, uint32_t n_sweeps, doub
 {
     if (!ctx || !mean_ms || !launches) return fail(ISLF_EINVAL, "NULL argument");
     if (n_sweeps < 1) return fail(ISLF_EINVAL, "n_sweeps must be >= 1");
-    islf_status st = prepare_plans(ctx, ISLF_EXEC_BATCHED);
+    islf_status st = sync_tables(ctx);
+    if (st == ISLF_OK && !ctx->batched.valid && !ctx->live.empty()) {
+        std::vector<Entry> S, M;
+        for (int r : ctx->live) {
+            S.insert(S.end(), ctx->reps[r].slab.begin(), ctx->reps[r].slab.end());
+            M.insert(M.end(), ctx->reps[r].main.begin(), ctx->reps[r].main.end());
+        }
+        st = build_plan(ctx, ctx->batched, S, M, ctx->grid_override ? ctx->grid_override : ctx->sweep_slots);
+    }
     if (st != ISLF_OK) return st;
     st = check_sweep_range(ctx, n_sweeps);
     if (st != ISLF_OK) return st;

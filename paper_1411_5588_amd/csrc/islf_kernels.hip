@@ -842,8 +842,12 @@ __device__ __forceinline__ void main_piece(const RepView &v, const Entry &en, in
 // order so that each XCD (and its L2) works on a contiguous run of tiles.
 __device__ __forceinline__ int plan_block()
 {
+    // workgroups go to the 8 XCDs in turn (block b to XCD b mod 8); XCD x
+    // takes the contiguous run of plan slots starting at x*q + min(x, r)
+    // (G = 8q + r), so that neighbouring pieces share its L2
     const int b = blockIdx.x, G = gridDim.x;
-    return (G & 7) ? b : (b & 7) * (G >> 3) + (b >> 3);
+    const int x = b & 7, q = G >> 3, r = G & 7;
+    return x * q + min(x, r) + (b >> 3);
 }
 
 template <int FMT, int KIND>

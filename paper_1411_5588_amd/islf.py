@@ -114,6 +114,8 @@ def lib():
             "islf_layer_profile": [vp, i32, vp],
             "islf_layer_profile_add": [vp, i32, vp],
             "islf_get_grid": [vp, P(i32)],
+            "islf_set_groups": [vp, i32],
+            "islf_get_groups": [vp, P(i32)],
             "islf_phase_timings": [vp, u32, vp, vp],
             "islf_replica_means": [vp, i32, u64, u32, vp],
         }
@@ -327,6 +329,15 @@ class Context:
     def set_grid(self, workgroups: int):
         """Workgroups per A / B launch (0 = two per resident slot)."""
         _check(lib().islf_set_grid(self._h, workgroups))
+
+    def set_groups(self, groups: int):
+        """Concurrent replica groups of the batched form (0 = min(4, live replicas))."""
+        _check(lib().islf_set_groups(self._h, groups))
+
+    def get_groups(self) -> int:
+        n = C.c_int32()
+        _check(lib().islf_get_groups(self._h, C.byref(n)))
+        return n.value
 
     def get_grid(self) -> int:
         n = C.c_int32()

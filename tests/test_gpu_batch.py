@@ -43,6 +43,35 @@ def test_graph_replay_equals_stream_launches(fmt, exec_mode):
         assert np.array_equal(spins[i], o_s), i
 
 
+@pytest.mark.parametrize("groups,grid", [(1, 0), (2, 0), (3, 96), (4, 0)])
+def test_concurrent_groups_graph_and_eager(groups, grid):
+    # the batched form with the replicas dealt into concurrent groups, each
+    # on its own stream (one graph per group); eager sweeps between replays
+    # and a change of the grouping in mid-run keep every chain exact
+    ps = batch_params()
+    with islf.Context([islf.Replica(**p) for p in ps], spin_format=islf.BITPACK, obs_capacity=64) as ctx:
+        ctx.set_groups(groups)
+        ctx.set_grid(grid)
+        assert ctx.get_groups() == groups
+        ctx.capture(3)
+        ctx.replay(2)
+        ctx.sweep(4)
+        ctx.replay(1)
+        ctx.set_groups(5 - groups)
+        with pytest.raises(islf.IslfError) as e:
+            ctx.replay(1)
+        assert e.value.status == islf.ESTATE
+        ctx.sweep(2)
+        ctx.capture(5)
+        ctx.replay(2)
+        recs = [ctx.measure(i, 0, 25) for i in range(len(ps))]
+        spins = [ctx.get_spins(i) for i in range(len(ps))]
+    for i, p in enumerate(ps):
+        _, o_rec, o_s = oracle_trajectory(p, 25)
+        assert np.array_equal(recs[i], o_rec), i
+        assert np.array_equal(spins[i], o_s), i
+
+
 def test_alone_equals_in_mix_with_admission_and_retirement():
     ps = batch_params()
     target = ps[1]
