@@ -81,12 +81,16 @@ extern "C" const char *islf_last_error(void) { return g_err.c_str(); }
 struct I8Tile {
     int tj_max, mx;
 };
+// tj_max = 0: linear tiles (a workgroup takes kBlock consecutive columns of
+// a plane's main rows in row-major order, whatever the row length)
 static const I8Tile kI8Tiles[] = {
     {16, 16}, {32, 16}, {64, 16}, {128, 16}, {256, 16}, {16, 8},  {32, 8},   {64, 8},
     {16, 32}, {32, 32}, {64, 32}, {128, 32}, {16, 64}, {32, 64}, {64, 64}, {256, 64},
+    {0, 16},  {0, 8},   {0, 32},
 };
 static const I8Tile kBpTilesM[] = {
     {16, 4}, {32, 4}, {64, 4}, {8, 4}, {4, 4}, {16, 2}, {16, 8}, {32, 8}, {8, 8}, {64, 8}, {4, 8}, {16, 16},
+    {0, 4},  {0, 2},  {0, 8},
 };
 static const int kNumBpTilesM = (int)(sizeof(kBpTilesM) / sizeof(kBpTilesM[0]));
 static const int kNumI8Tiles = (int)(sizeof(kI8Tiles) / sizeof(kI8Tiles[0]));
@@ -102,11 +106,15 @@ static I8Shape i8_shape(const islf_replica_desc &d, int tile, int fmt = ISLF_SPI
 {
     const long C = fmt == ISLF_SPIN_INT8 ? (d.Lz + 7) / 8 : (d.Lz + 63) / 64;
     const I8Tile &t = fmt == ISLF_SPIN_INT8 ? kI8Tiles[tile] : kBpTilesM[tile];
-    const long pieces = ceil_div(C, t.tj_max);
     I8Shape s;
+    s.mx = std::min(t.mx, d.Lx);
+    if (t.tj_max == 0) {
+        s.tj = s.ty = 0;
+        return s;
+    }
+    const long pieces = ceil_div(C, t.tj_max);
     s.tj = (int)ceil_div(C, pieces);
     s.ty = (int)std::min<long>(kBlock / s.tj, std::max(1, d.Ly - 3));
-    s.mx = std::min(t.mx, d.Lx);
     return s;
 }
 
@@ -117,7 +125,9 @@ static double tile_efficiency(const islf_replica_desc &d, int fmt, int tile)
     if (ny <= 0) return 1.0;
     const long C = fmt == ISLF_SPIN_INT8 ? (d.Lz + 7) / 8 : (d.Lz + 63) / 64;
     const I8Shape s = i8_shape(d, tile, fmt);
-    const double entries = (double)ceil_div(d.Lx, s.mx) * ceil_div((long)ny, s.ty) * ceil_div(C, s.tj);
+    const double per_plane = s.tj == 0 ? (double)ceil_div((long)ny * C, kBlock)
+                                       : (double)ceil_div((long)ny, s.ty) * ceil_div(C, s.tj);
+    const double entries = (double)ceil_div(d.Lx, s.mx) * per_plane;
     return (double)d.Lx * ny * C / (entries * kBlock * s.mx);
 }
 
@@ -329,10 +339,19 @@ static void build_work(Replica &R, int rep_id, int fmt)
     R.slab.clear();
     const int J = fmt == ISLF_SPIN_INT8 ? (d.Lz + 7) / 8 : (d.Lz + 63) / 64;
     const I8Shape s = i8_shape(d, R.tile, fmt);
-    for (int x0 = 0; x0 < d.Lx; x0 += s.mx)
+    const int cols = std::max(0, d.Ly - 3) * J;   // main columns of a plane (rows 2 .. Ly-2)
+    for (int x0 = 0; x0 < d.Lx; x0 += s.mx) {
+        if (s.tj == 0) {
+            // linear tile: y0 = first column, j0 = end of the range
+            for (int c0 = 0; c0 < cols; c0 += kBlock)
+                R.main.push_back(Entry{rep_id, x0, c0, std::min(c0 + kBlock, cols), std::min(s.mx, d.Lx - x0),
+                                       ITEM_MAIN});
+            continue;
+        }
         for (int y0 = 2; y0 < d.Ly - 1; y0 += s.ty)
             for (int j0 = 0; j0 < J; j0 += s.tj)
                 R.main.push_back(Entry{rep_id, x0, y0, j0, std::min(s.mx, d.Lx - x0), ITEM_MAIN});
+    }
     R.d.i8_tj = s.tj;
     R.d.i8_ty = s.ty;
     R.d.i8_mx = s.mx;
@@ -796,7 +815,12 @@ extern "C" islf_status islf_create_with_allocator(const islf_replica_desc *reps,
     if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, persistent_kernel(spin_format), kBlock, 0) != hipSuccess ||
         per_cu < 1)
         per_cu = 1;
-    c->persistent_grid = std::min(c->num_cu * std::min(per_cu, 8), kBarrierGroup * kMaxGroups);
+    // one slot per CU stays free: at the full theoretical occupancy (7
+    // workgroups per CU for a 72-VGPR kernel) a cooperative launch was
+    // accepted but its workgroups were not all resident at once, and the grid
+    // barrier's bounded wait expired
+    const int per_cu_p = per_cu > 1 ? per_cu - 1 : 1;
+    c->persistent_grid = std::min(c->num_cu * std::min(per_cu_p, 8), kBarrierGroup * kMaxGroups);
     c->d_sync = (GridSync *)dev_alloc(c, sizeof(GridSync));
     c->d_scratch = (unsigned long long *)dev_alloc(c, 64 * sizeof(unsigned long long));
     if (!c->d_sync || !c->d_scratch) {
@@ -1049,7 +1073,7 @@ static islf_status check_device_error(islf_ctx *c)
         // clear it so that the context stays usable
         HIP_TRY(launch_zero((unsigned long long *)&c->d_sync->error, 16, c->stream));
         HIP_TRY(hipStreamSynchronize(c->stream));
-        return fail(ISLF_EDEVICE, "a persistent-kernel barrier timed out");
+        return fail(ISLF_EDEVICE, "a persistent-kernel barrier timed out (its workgroups were not all resident at once)");
     }
     return ISLF_OK;
 }

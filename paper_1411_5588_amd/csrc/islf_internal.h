@@ -20,8 +20,10 @@ constexpr int kMaxMarch = 256;       // x planes one thread may march through pe
 // One item of work for one replica.  j counts 8-byte chunks (int8 format) or
 // 32-bit words of one sublattice row (bit-packed).
 // Main tile (kind 0, rows 2 .. Ly-2): a box of rows/columns starting at
-// (x0, y0, j0) whose extent is the replica's tile shape, marched through
-// nsteps x planes from x0 (a launch plan may cut a tile into pieces along x).
+// (x0, y0, j0) whose extent is the replica's tile shape, or (linear tile
+// shape, i8_tj = 0) the columns [y0, j0) of a plane's main rows in row-major
+// order, marched through nsteps x planes from x0 (a launch plan may cut a
+// tile into pieces along x).
 // Seam-slab tile (kind 1, rows Ly-1, 0, 1): x0 = first x pair p (planes p and
 // Lx-1-p), y0 = number of consecutive pairs, j0 = first column,
 // nsteps = number of columns.
@@ -53,7 +55,7 @@ struct RepDesc {
     int32_t seam_invert;   // 1: the y seam carries eps = -1
     uint32_t key0, key1, replica, cap;
     int32_t fmt;                   // islf_spin_format
-    int32_t i8_tj, i8_ty, i8_mx;   // main tiles: columns x rows per workgroup, x planes marched
+    int32_t i8_tj, i8_ty, i8_mx;   // main tiles: columns x rows per workgroup (0 x 0: linear), x planes marched
     double J, H, h1, hn;           // for energies (Eq. 1)
 };
 

@@ -131,8 +131,8 @@ struct RepView {
     uint32_t Lzp;           // int8 row stride in bytes
     int seam_reflect, seam_invert;
     uint32_t key0, key1, replica, t;
-    int tj, ty, mx;          // marching tile
-    int my_ty, my_tj;        // this thread's row and column inside the tile
+    int tj, ty, mx;          // marching tile (tj = 0: linear tiles)
+    int my_ty, my_tj;        // this thread's row and column inside a box tile
     bool never;              // some move can never be accepted (thr == 0)
 };
 
@@ -152,7 +152,7 @@ __device__ __forceinline__ RepView load_view(const RepDesc *__restrict__ descs, 
     v.tj = d.i8_tj;
     v.ty = d.i8_ty;
     v.mx = d.i8_mx;
-    v.my_ty = (int)threadIdx.x / v.tj;
+    v.my_ty = v.tj > 0 ? (int)threadIdx.x / v.tj : 0;
     v.my_tj = (int)threadIdx.x - v.my_ty * v.tj;
     v.never = d.never_mask != 0;
     return v;
@@ -384,14 +384,31 @@ __device__ __forceinline__ StepIn load_step(const RepView &v, const MarchLane &L
 // index 4*(cnt + 8u + 16*class) is formed with word-wide adds; a shift by 8q
 // moves the four sites of the phase to bytes 0, 2, 4, 6.  A flip adds its
 // packed (dB, dM) change to a register sum.
+// The column a thread of a main tile marches: row y (2 .. Ly-2) and column j
+// (< ncol chunks or words), or false when the thread has none.  A box tile
+// is v.ty rows x v.tj columns from (en.y0, en.j0); a linear tile (v.tj = 0)
+// is the range [en.y0, en.j0) of the plane's main columns in row-major order,
+// one per thread.
+__device__ __forceinline__ bool main_column(const RepView &v, const Entry &en, int ncol, int &y, int &j)
+{
+    if (v.tj > 0) {
+        y = en.y0 + v.my_ty;
+        j = en.j0 + v.my_tj;
+        return v.my_ty < v.ty && y < v.Ly - 1 && j < ncol;
+    }
+    const int lin = en.y0 + (int)threadIdx.x;
+    const int r = (int)((uint32_t)lin / (uint32_t)ncol);
+    y = 2 + r;
+    j = lin - r * ncol;
+    return lin < en.j0;
+}
+
 template <bool NEVER, bool RAGGED>
 __device__ __forceinline__ void i8_march(const RepView &v, const Entry &en, int k_lo, int k_hi, int parity,
                                          const Tables *tb, Acc &a)
 {
-    const int ty = v.my_ty, tj = v.my_tj;
-    const int y = en.y0 + ty;
-    const int j = en.j0 + tj;
-    if (ty >= v.ty || y >= v.Ly - 1 || j >= v.C) return;   // main rows are 2 .. Ly-2
+    int y, j;
+    if (!main_column(v, en, v.C, y, j)) return;
     const int Lx = v.Lx, Ly = v.Ly, C = v.C, Lz = v.Lz;
     const uint32_t Lzp = v.Lzp;
     const int x0 = en.x0 + k_lo;
@@ -613,10 +630,8 @@ template <bool NEVER>
 __device__ __forceinline__ void bp_march(const RepView &v, const Entry &en, int k_lo, int k_hi, int parity,
                                          const Tables *tb, Acc &a)
 {
-    const int ty = v.my_ty, tj = v.my_tj;
-    const int y = en.y0 + ty;
-    const int w = en.j0 + tj;
-    if (ty >= v.ty || y >= v.Ly - 1 || w >= v.Wq) return;   // main rows are 2 .. Ly-2
+    int y, w;
+    if (!main_column(v, en, v.Wq, y, w)) return;
     const int Lx = v.Lx, Ly = v.Ly, C = v.C, Wq = v.Wq;
     const int nbits = v.Lz >> 1;
     const uint32_t SB = 4u * (uint32_t)Wq;    // bytes of one sublattice row

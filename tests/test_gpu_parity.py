@@ -108,8 +108,12 @@ def test_random_shapes_all_boundaries(fmt):
 
 
 @pytest.mark.parametrize("fmt", FORMATS)
-def test_every_tile_variant_gives_the_same_chain(fmt):
-    p = config1(Lx=7, Ly=13, Lz=90, replica=5)
+@pytest.mark.parametrize("shape", [(7, 13, 90), (4, 90, 202)])
+def test_every_tile_variant_gives_the_same_chain(fmt, shape):
+    # (4, 90, 202): several linear tiles per plane with a ragged last one, a
+    # ragged int8 row (202 = 8 x 25 + 2) and a partial last bit-packed word
+    Lx, Ly, Lz = shape
+    p = config1(Lx=Lx, Ly=Ly, Lz=Lz, replica=5)
     n = 6
     o_s0, o_rec, o_s1 = oracle_trajectory(p, n)
     for tile in range(islf.num_tiles(fmt)):
