@@ -239,6 +239,28 @@ islf_status islf_get_tile(const islf_ctx *ctx, int32_t rep, int32_t *tile);
 islf_status islf_set_tile(islf_ctx *ctx, int32_t rep, int32_t tile);
 islf_status islf_autotune(islf_ctx *ctx, uint32_t sweeps);
 
+/* Launch-plan preview, host only (no device, no context): the work items of
+ * n_reps replicas (tile variant `tile`, or each replica's default with -1)
+ * cut into the plan of one launch chain of `grid` workgroups, as the batched
+ * form builds it.  For checking plans and choosing grids.
+ *   shapes (optional, 4 x n_reps int32): per replica (tile variant, columns
+ *     per box tile or 0 for a linear tile, rows per box tile, x planes per
+ *     tile).
+ *   items (optional, 6 x items_cap int32): per item (replica, x0, y0, j0,
+ *     x steps, kind), kind 0 = main tile, 1 = seam-slab tile; a main tile's
+ *     (y0, j0) is its first row and column (box) or its column range [y0, j0)
+ *     over the plane's main rows 2 .. Ly-2 in row-major order (linear); a
+ *     slab tile's x0, y0, j0, x steps are its first x pair, pairs, first
+ *     column and columns.
+ *   first (optional, first_cap int32): workgroup b runs items
+ *     [first[b], first[b+1]); slab items sit in the first workgroups.
+ * *n_items and *n_first receive the counts (query them with NULL buffers).
+ * Errors: EINVAL (NULL count pointers, bad replica, format, tile or grid),
+ * ERANGE (a buffer is smaller than its count; the counts are still set). */
+islf_status islf_plan_preview(const islf_replica_desc *descs, int32_t n_reps, int32_t spin_format, int32_t tile,
+                              int32_t grid, int32_t *shapes, int32_t *items, int32_t items_cap, int32_t *n_items,
+                              int32_t *first, int32_t first_cap, int32_t *n_first);
+
 /* Layer profile of one replica's current spins (Sec. II.B, Eq. 17): for
  * every row (x, y), P[x*Ly + y] = sum over z of S(x, y, z), i.e. Lz times the
  * paper's row magnetisation m_{k_x}(y).  islf_layer_profile writes P to

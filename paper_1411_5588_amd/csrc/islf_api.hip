@@ -1223,6 +1223,53 @@ extern "C" islf_status islf_footprint_bytes(const islf_replica_desc *desc, int32
     return ISLF_OK;
 }
 
+extern "C" islf_status islf_plan_preview(const islf_replica_desc *descs, int32_t n_reps, int32_t spin_format,
+                                         int32_t tile, int32_t grid, int32_t *shapes, int32_t *items,
+                                         int32_t items_cap, int32_t *n_items, int32_t *first, int32_t first_cap,
+                                         int32_t *n_first)
+{
+    if (!descs || !n_items || !n_first) return fail(ISLF_EINVAL, "NULL argument");
+    if (n_reps < 1) return fail(ISLF_EINVAL, "n_reps must be >= 1");
+    if (spin_format != ISLF_SPIN_INT8 && spin_format != ISLF_SPIN_BITPACK)
+        return fail(ISLF_EINVAL, "invalid spin format %d", spin_format);
+    if (tile < -1 || tile >= num_tiles_of(spin_format)) return fail(ISLF_EINVAL, "invalid tile %d", tile);
+    if (grid < 1 || grid > (1 << 20)) return fail(ISLF_EINVAL, "invalid workgroup count %d", grid);
+    if (items_cap < 0 || first_cap < 0) return fail(ISLF_EINVAL, "negative capacity");
+    std::vector<Entry> S, M;
+    for (int r = 0; r < n_reps; ++r) {
+        islf_status st = validate(descs + r);
+        if (st != ISLF_OK) return st;
+        Replica R;
+        R.desc = descs[r];
+        R.tile = tile >= 0 ? tile : default_tile(descs + r, spin_format);
+        build_work(R, r, spin_format);
+        if (shapes) {
+            shapes[4 * r + 0] = R.tile;
+            shapes[4 * r + 1] = R.d.i8_tj;
+            shapes[4 * r + 2] = R.d.i8_ty;
+            shapes[4 * r + 3] = R.d.i8_mx;
+        }
+        S.insert(S.end(), R.slab.begin(), R.slab.end());
+        M.insert(M.end(), R.main.begin(), R.main.end());
+    }
+    std::vector<Entry> it;
+    std::vector<int> fi;
+    partition_items(S, M, grid, it, fi);
+    *n_items = (int32_t)it.size();
+    *n_first = (int32_t)fi.size();
+    if ((items && (int64_t)it.size() > items_cap) || (first && (int64_t)fi.size() > first_cap))
+        return fail(ISLF_ERANGE, "plan needs %zu items and %zu offsets", it.size(), fi.size());
+    if (items)
+        for (size_t i = 0; i < it.size(); ++i) {
+            const Entry &e = it[i];
+            const int32_t v[6] = {e.rep, e.x0, e.y0, e.j0, e.nsteps, e.kind};
+            for (int k = 0; k < 6; ++k) items[6 * i + k] = v[k];
+        }
+    if (first)
+        for (size_t i = 0; i < fi.size(); ++i) first[i] = fi[i];
+    return ISLF_OK;
+}
+
 extern "C" islf_status islf_batch_add(islf_ctx *ctx, const islf_replica_desc *desc, int32_t *slot)
 {
     if (!ctx || !slot) return fail(ISLF_EINVAL, "NULL argument");

@@ -102,6 +102,7 @@ def lib():
             "islf_means": [vp, u64, u32, vp],
             "islf_integrate": [vp, vp, vp, i32, dbl, dbl, dbl, vp, vp],
             "islf_footprint_bytes": [P(ReplicaDesc), i32, u32, P(u64)],
+            "islf_plan_preview": [vp, i32, i32, i32, i32, vp, vp, i32, P(i32), vp, i32, P(i32)],
             "islf_batch_add": [vp, P(ReplicaDesc), P(i32)],
             "islf_batch_retire": [vp, i32],
             "islf_graph_capture": [vp, u32],
@@ -365,6 +366,26 @@ def footprint_bytes(replica: Replica, spin_format=INT8, obs_capacity=1024) -> in
     d = replica.to_c()
     _check(lib().islf_footprint_bytes(C.byref(d), spin_format, obs_capacity, C.byref(b)))
     return b.value
+
+
+def plan_preview(replicas, spin_format=INT8, tile=-1, grid=2048):
+    """The batched form's launch plan for these replicas as one launch chain
+    of `grid` workgroups, computed on the host (no GPU): a dict with
+    `shapes` (n, 4) = (tile variant, box columns or 0 for linear, box rows,
+    x planes), `items` (k, 6) = (replica, x0, y0, j0, x steps, kind) and
+    `first` (workgroup b runs items first[b] .. first[b+1]-1)."""
+    n = len(replicas)
+    descs = (ReplicaDesc * n)(*[r.to_c() for r in replicas])
+    ni, nf = C.c_int32(), C.c_int32()
+    _check(lib().islf_plan_preview(descs, n, spin_format, tile, grid, None, None, 0, C.byref(ni), None, 0,
+                                   C.byref(nf)))
+    shapes = np.zeros((n, 4), dtype=np.int32)
+    items = np.zeros((max(ni.value, 1), 6), dtype=np.int32)
+    first = np.zeros(max(nf.value, 1), dtype=np.int32)
+    _check(lib().islf_plan_preview(descs, n, spin_format, tile, grid, shapes.ctypes.data_as(C.c_void_p),
+                                   items.ctypes.data_as(C.c_void_p), items.shape[0], C.byref(ni),
+                                   first.ctypes.data_as(C.c_void_p), first.shape[0], C.byref(nf)))
+    return {"shapes": shapes, "items": items[:ni.value], "first": first[:nf.value]}
 
 
 def integrate(h, m1, mn, c1=-1.0, cn=1.0, norm=1.0, stream=None):

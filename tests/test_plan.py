@@ -1,0 +1,165 @@
+"""Launch plans, checked on the host (no GPU).
+
+islf_plan_preview returns the items of the batched form's launch plan and
+their split over workgroups.  Emulating each item's thread-to-site mapping
+(box or linear main tiles, seam-slab tiles) shows that one launch touches
+every site column of every replica exactly once: each main-row column
+(x, y, j) for y in 2 .. Ly-2 in one main piece, each seam-slab column
+(x pair, j) in one slab tile.  The split keeps slab items in the first
+workgroups, ahead of that workgroup's main pieces, and keeps every
+workgroup's cost near its share.
+"""
+import os
+
+import numpy as np
+import pytest
+
+from paper_1411_5588_amd import islf
+
+BLOCK = 256
+
+SMALL_SHAPES = [(1, 2, 2), (1, 5, 18), (2, 3, 64), (3, 7, 66), (5, 40, 202), (7, 13, 90), (4, 90, 202),
+                (2, 300, 30)]
+GRIDS = [1, 7, 64, 1000]
+
+
+@pytest.fixture(scope="module", autouse=True)
+def built():
+    if not os.path.exists(islf.LIB_PATH):
+        from paper_1411_5588_amd import build
+        build.build()
+
+
+def columns(Lz, fmt):
+    return (Lz + 7) // 8 if fmt == islf.INT8 else (Lz + 63) // 64
+
+
+def main_sites(item, shape, Ly, J):
+    """(y, j) arrays of the threads of a main piece that own a column."""
+    _, x0, y0, j0, nsteps, kind = item
+    _, tj, ty, mx = shape
+    t = np.arange(BLOCK)
+    if tj > 0:
+        my_ty, my_tj = t // tj, t % tj
+        y, j = y0 + my_ty, j0 + my_tj
+        ok = (my_ty < ty) & (y < Ly - 1) & (j < J)
+    else:
+        lin = y0 + t
+        y, j = 2 + lin // J, lin % J
+        ok = lin < j0
+    return y[ok], j[ok]
+
+
+def check_plan(reps, fmt, tile, grid):
+    plan = islf.plan_preview(reps, fmt, tile=tile, grid=grid)
+    items, first, shapes = plan["items"], plan["first"], plan["shapes"]
+    # the split: offsets run 0 .. n_items, at most one run per workgroup
+    assert first[0] == 0 and first[-1] == len(items)
+    assert np.all(np.diff(first) >= 0)
+    assert len(first) - 1 <= grid
+    # per replica: every main column and every slab column exactly once
+    main_cnt, slab_cnt = [], []
+    for r in reps:
+        J = columns(r.Lz, fmt)
+        main_cnt.append(np.zeros((r.Lx, r.Ly, J), dtype=np.int32))
+        slab_cnt.append(np.zeros(((r.Lx + 1) // 2, J), dtype=np.int32))
+    for it in items:
+        rep, x0, y0, j0, nsteps, kind = (int(v) for v in it)
+        r = reps[rep]
+        J = columns(r.Lz, fmt)
+        assert nsteps >= 1
+        if kind == 1:
+            # slab tile: pairs [x0, x0 + y0) x columns [j0, j0 + nsteps); one
+            # row stage has at most one task per thread pair
+            assert y0 >= 1 and y0 * nsteps <= BLOCK // 2
+            slab_cnt[rep][x0:x0 + y0, j0:j0 + nsteps] += 1
+        else:
+            assert kind == 0
+            assert 0 <= x0 and x0 + nsteps <= r.Lx and nsteps <= shapes[rep][3]
+            y, j = main_sites(it, shapes[rep], r.Ly, J)
+            assert np.all((y >= 2) & (y <= r.Ly - 2) & (j >= 0) & (j < J))
+            for x in range(x0, x0 + nsteps):
+                np.add.at(main_cnt[rep], (x, y, j), 1)
+    for i, r in enumerate(reps):
+        mc = main_cnt[i]
+        assert np.all(mc[:, 2:r.Ly - 1, :] == 1), f"main coverage, replica {i}"
+        assert np.all(mc[:, :2, :] == 0) and np.all(mc[:, r.Ly - 1:, :] == 0)
+        assert np.all(slab_cnt[i] == 1), f"slab coverage, replica {i}"
+    # slab items only in the first workgroups, each ahead of the main pieces
+    n_slab = int(np.sum(items[:, 5] == 1))
+    gs = min(grid, n_slab)
+    for b in range(len(first) - 1):
+        kinds = items[first[b]:first[b + 1], 5]
+        if b >= gs:
+            assert np.all(kinds == 0), b
+        k = int(np.argmax(kinds == 0)) if np.any(kinds == 0) else len(kinds)
+        assert np.all(kinds[:k] == 1) and np.all(kinds[k:] == 0), b
+    # balance: a main step costs 4 units, a slab tile 6 per row-stage task
+    # round of the workgroup; shares are tapered by +-20% over dispatch rank
+    cost = np.zeros(len(first) - 1)
+    slab_unit = 0
+    for b in range(len(first) - 1):
+        for it in items[first[b]:first[b + 1]]:
+            if it[5] == 1:
+                c = 6 * ((6 * int(it[2]) * int(it[4]) + BLOCK - 1) // BLOCK)
+                slab_unit = max(slab_unit, c)
+            else:
+                c = 4 * int(it[4])
+            cost[b] += c
+    W = cost.sum()
+    assert cost.max() <= 1.2 * W / grid + 4 + slab_unit + 1e-9
+    return plan
+
+
+@pytest.mark.parametrize("fmt", [islf.INT8, islf.BITPACK])
+@pytest.mark.parametrize("shape", SMALL_SHAPES)
+def test_every_tile_variant_covers_each_site_once(fmt, shape):
+    Lx, Ly, Lz = shape
+    reps = [islf.Replica(Lx, Ly, Lz, islf.GAPBC)]
+    for tile in range(islf.num_tiles(fmt)):
+        for grid in GRIDS:
+            check_plan(reps, fmt, tile, grid)
+
+
+@pytest.mark.parametrize("fmt", [islf.INT8, islf.BITPACK])
+def test_mixed_batch_and_paper_scale(fmt):
+    mixed = [islf.Replica(*s, islf.GAPBC, replica=i) for i, s in enumerate([(5, 40, 202), (1, 2, 2), (7, 13, 90),
+                                                                            (40, 120, 120), (20, 64, 64)])]
+    for grid in (1, 13, 512, 2048, 5000):
+        check_plan(mixed, fmt, -1, grid)
+    check_plan([islf.Replica(160, 480, 600, islf.GAPBC)], fmt, -1, 2048)
+
+
+def test_default_tile_prefers_full_lanes():
+    # 477 main rows of 10 bit-packed words: a box of 10 x 25 leaves 7% of its
+    # lane-steps idle, the linear tile 2%
+    p = islf.plan_preview([islf.Replica(160, 480, 600, islf.GAPBC)], islf.BITPACK, grid=64)
+    assert p["shapes"][0][1] == 0
+    # a box that fills its lanes exactly is kept (ties go to the box)
+    p = islf.plan_preview([islf.Replica(8, 67, 512, islf.GAPBC)], islf.INT8, grid=64)
+    tj, ty = p["shapes"][0][1], p["shapes"][0][2]
+    assert tj > 0 and tj * ty == BLOCK and 64 % tj == 0 and 64 % ty == 0
+
+
+def test_plan_preview_errors():
+    r = [islf.Replica(4, 6, 8)]
+    for kw in (dict(spin_format=7), dict(tile=99), dict(tile=-2), dict(grid=0)):
+        args = dict(spin_format=islf.INT8, tile=-1, grid=8)
+        args.update(kw)
+        with pytest.raises(islf.IslfError) as e:
+            islf.plan_preview(r, **args)
+        assert e.value.status == islf.EINVAL
+    with pytest.raises(islf.IslfError) as e:
+        islf.plan_preview([islf.Replica(4, 1, 8)], islf.INT8)
+    assert e.value.status == islf.EINVAL
+
+
+def test_xcd_mapping_is_a_bijection():
+    # the kernel's workgroup-to-run map: XCD x = b mod 8 takes the runs from
+    # x*q + min(x, r), G = 8q + r
+    for G in list(range(1, 70)) + [683, 1280, 2048, 2049]:
+        q, r = divmod(G, 8)
+        b = np.arange(G)
+        x = b % 8
+        runs = x * q + np.minimum(x, r) + b // 8
+        assert sorted(runs.tolist()) == list(range(G))
