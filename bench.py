@@ -310,6 +310,7 @@ def main():
     chain_ms = 0.5 * (kms["A"] + kms["B"])
     chain_tops = OPS_PER_UPDATE * updates_per_wave / (chain_ms * 1e-3) / 1e12
     traffic = committed_traffic(args.fmt)
+    alg_gbs = BYTES_PER_UPDATE[args.fmt] * updates_per_wave / (wave_ms * 1e-3) / 1e9
     roofline = {"bound": "alu", "achieved": round(achieved_tops, 2), "peak": round(VALU_PEAK_TOPS, 1),
                 "unit": "T int-op/s", "frac": round(achieved_tops / VALU_PEAK_TOPS, 4), "traffic": traffic,
                 "kernel": "k_sweep (A and B launches)",
@@ -318,9 +319,8 @@ def main():
                 "wave_ms": round(wave_ms, 5), "ops_per_update": OPS_PER_UPDATE,
                 "single_chain": {"kernel_ms": round(chain_ms, 5), "workgroups": kms.get("grid"),
                                  "achieved": round(chain_tops, 2), "frac": round(chain_tops / VALU_PEAK_TOPS, 4)},
-                "hbm_view": {"algorithmic_GBs": round(BYTES_PER_UPDATE[args.fmt] * updates_per_wave
-                                                      / (wave_ms * 1e-3) / 1e9, 1),
-                             "peak_GBs": HBM_PEAK_GBS}}
+                "hbm_view": {"algorithmic_GBs": round(alg_gbs, 1), "peak_GBs": HBM_PEAK_GBS,
+                             "frac": round(alg_gbs / HBM_PEAK_GBS, 4)}}
 
     prof = layer_profile_rate(islf, torch)
     print(f"# layer profile: {prof}", file=sys.stderr, flush=True)
