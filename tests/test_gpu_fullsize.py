@@ -46,15 +46,24 @@ def oracle_T3():
     yield p, th, out
 
 
-@pytest.mark.parametrize("fmt,exec_mode", [(islf.INT8, islf.EXEC_BATCHED), (islf.BITPACK, islf.EXEC_BATCHED),
-                                           (islf.INT8, islf.EXEC_PERSISTENT), (islf.INT8, islf.EXEC_PLAIN)])
-def test_paper_scale_two_sweeps_bit_exact(oracle_T3, fmt, exec_mode):
+@pytest.mark.parametrize("fmt,exec_mode,graph", [(islf.INT8, islf.EXEC_BATCHED, False),
+                                                 (islf.BITPACK, islf.EXEC_BATCHED, False),
+                                                 (islf.BITPACK, islf.EXEC_BATCHED, True),
+                                                 (islf.INT8, islf.EXEC_PERSISTENT, False),
+                                                 (islf.INT8, islf.EXEC_PLAIN, False)])
+def test_paper_scale_two_sweeps_bit_exact(oracle_T3, fmt, exec_mode, graph):
     p, th, out = oracle_T3
-    # the batch the benchmark runs: T = 2, 3, 4 side by side
+    # the batch the benchmark runs: T = 2, 3, 4 side by side, in its default
+    # launch configuration (concurrent replica groups); graph: captured and
+    # replayed as the benchmark does
     reps = [islf.Replica(**params(T, i)) for i, T in enumerate((2.0, 3.0, 4.0))]
     with islf.Context(reps, spin_format=fmt, obs_capacity=16, exec_mode=exec_mode) as ctx:
         s0 = ctx.get_spins(1)
-        ctx.sweep(2)
+        if graph:
+            ctx.capture(2)
+            ctx.replay(1)
+        else:
+            ctx.sweep(2)
         rec = ctx.measure(1, 0, 2)
         s2 = ctx.get_spins(1)
         rc = ctx.recompute(1)
