@@ -60,8 +60,8 @@ KERNEL_SOURCE = os.path.join(ROOT, "paper_1411_5588_amd", "csrc", "islf_kernels.
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=400)
-    ap.add_argument("--warmup", type=int, default=50)
+    ap.add_argument("--steps", type=int, default=2000)
+    ap.add_argument("--warmup", type=int, default=200)
     ap.add_argument("--chunk", type=int, default=50, help="sweeps per captured graph launch")
     ap.add_argument("--groups", type=int, default=0,
                     help="concurrent replica groups of the batched form (0: automatic, 1: one launch chain)")
