@@ -68,7 +68,9 @@ typedef enum { ISLF_INIT_RANDOM = 0, ISLF_INIT_UP = 1, ISLF_INIT_DOWN = 2, ISLF_
  * small fold launch closes the run's last record.
  *  PLAIN      : the A and B launches go one replica at a time (one lattice
  *               per launch).
- *  BATCHED    : each A and B launch covers every replica.
+ *  BATCHED    : each A and B launch covers every replica of a concurrent
+ *               replica group (islf_set_groups); the groups' launch chains
+ *               run side by side on their own streams.
  *  PERSISTENT : one launch for all requested sweeps of every replica, with
  *               device-side grid barriers in place of the launch boundaries. */
 typedef enum { ISLF_EXEC_PLAIN = 0, ISLF_EXEC_BATCHED = 1, ISLF_EXEC_PERSISTENT = 2 } islf_exec;
@@ -106,8 +108,9 @@ typedef void (*islf_free_fn)(void *ptr, void *user);
  * format, each with a ring of obs_capacity (>= 3) per-sweep records, and
  * initialises every replica per its init field (ISLF_INIT_HOST starts all-up
  * until islf_set_spins is called).  hip_stream (hipStream_t, may be NULL for
- * the default stream) is borrowed: all device work of this context is issued
- * on it.  Device memory comes from alloc/free if given, else hipMalloc.  On
+ * the default stream) is borrowed: all device work of this context is ordered
+ * on it (the batched form's group streams fork from it and join back to it
+ * within each call).  Device memory comes from alloc/free if given, else hipMalloc.  On
  * failure nothing stays allocated and *out is NULL.
  * Errors: EINVAL (shape, n_reps, capacity, format), ERANGE (lattice too large
  * for the 32-bit Philox group counter), ENOMEM, EDEVICE. */
@@ -121,10 +124,11 @@ islf_status islf_create_with_allocator(const islf_replica_desc *reps, int32_t n_
 /* Synchronises the context's stream and releases everything it owns. */
 islf_status islf_destroy(islf_ctx *ctx);
 
-/* Number of replica slots and whether slot `rep` holds a live replica. */
+/* Number of replica slots, live or retired (slot indices run 0 .. n-1). */
 islf_status islf_num_replicas(const islf_ctx *ctx, int32_t *n);
 
-/* Copies the replica's parameters as given at creation. */
+/* Copies a live replica's parameters as given at creation (ERANGE if the
+ * slot is not live, so this also tells whether a slot holds a replica). */
 islf_status islf_get_desc(const islf_ctx *ctx, int32_t rep, islf_replica_desc *out);
 
 /* Host <-> device spins, int8 +-1 in the host layout above; n must equal
