@@ -21,8 +21,8 @@ wave of concurrent dispatches that together update half a sweep of every
 replica.  The roofline's unit is that launch wave: its algorithmic operations
 over its average duration, i.e. the timed region (HIP events on the
 context's stream, which forks to and joins from the group streams) divided by
-the waves in it.  The per-launch time of a single launch chain over all
-replicas (HIP events around each launch) is reported beside it.
+the waves in it.  The same form run as one launch chain over all replicas,
+timed the same way, gives the sweep kernel's own per-launch time beside it.
 """
 from __future__ import annotations
 
@@ -87,7 +87,7 @@ def replicas(islf, n=None):
                          seed=SEED + i, replica=i, init=islf.INIT_RANDOM) for i in range(n)]
 
 
-def run_form(islf, torch, form, fmt, steps, warmup, chunk, timings=False, n_reps=None, groups=0):
+def run_form(islf, torch, form, fmt, steps, warmup, chunk, n_reps=None, groups=0):
     mode = {"persistent": islf.EXEC_PERSISTENT, "batched": islf.EXEC_BATCHED, "plain": islf.EXEC_PLAIN}[form]
     f = {"int8": islf.INT8, "bitpack": islf.BITPACK}[fmt]
     reps = replicas(islf, n_reps)
@@ -119,15 +119,8 @@ def run_form(islf, torch, form, fmt, steps, warmup, chunk, timings=False, n_reps
         total_ms = t0.elapsed_time(t1)
         for i in range(len(reps)):
             assert ctx.sweep_count(i) == warmup + steps
-        out = dict(ms_per_sweep=total_ms / steps, sweeps_per_launch=chunk, launches=n_launch,
-                   groups=ctx.get_groups() if form == "batched" else 1, grid=ctx.get_grid())
-        if timings:
-            # per-launch times of one launch chain over all replicas
-            ctx.set_groups(1)
-            ms, cnt = ctx.phase_timings(8)
-            out["kernel_ms"] = {"A": float(ms[0]), "B": float(ms[1]), "close": float(ms[2]), "grid": ctx.get_grid()}
-            out["kernel_launches"] = [int(c) for c in cnt]
-        return out
+        return dict(ms_per_sweep=total_ms / steps, sweeps_per_launch=chunk, launches=n_launch,
+                    groups=ctx.get_groups() if form == "batched" else 1, grid=ctx.get_grid())
     finally:
         ctx.close()
 
@@ -276,10 +269,16 @@ def main():
     n_reps = len(TEMPS)
     updates_per_sweep = N * n_reps
 
-    main_run = run_form(islf, torch, args.form, args.fmt, args.steps, args.warmup, args.chunk, timings=True,
-                        groups=args.groups)
+    main_run = run_form(islf, torch, args.form, args.fmt, args.steps, args.warmup, args.chunk, groups=args.groups)
     print(f"# {args.form}/{args.fmt}: {main_run}", file=sys.stderr, flush=True)
     value = updates_per_sweep / (main_run["ms_per_sweep"] * 1e6)
+    # the same form as one launch chain over all replicas, timed the same way
+    if main_run["groups"] == 1:
+        chain_run = main_run
+    else:
+        chain_run = run_form(islf, torch, args.form, args.fmt, min(args.steps, 400), min(args.warmup, 100),
+                             args.chunk, groups=1)
+        print(f"# {args.form}/{args.fmt} one launch chain: {chain_run}", file=sys.stderr, flush=True)
 
     forms = {}
     if not args.no_extras:
@@ -305,9 +304,9 @@ def main():
     updates_per_wave = n_reps * N / 2
     wave_ms = main_run["ms_per_sweep"] / 2
     achieved_tops = OPS_PER_UPDATE * updates_per_wave / (wave_ms * 1e-3) / 1e12
-    # one launch chain over all replicas, HIP events around each launch
-    kms = main_run["kernel_ms"]
-    chain_ms = 0.5 * (kms["A"] + kms["B"])
+    # one launch chain over all replicas: its launches run one after another,
+    # so the same quotient is the sweep kernel's own per-launch time
+    chain_ms = chain_run["ms_per_sweep"] / 2
     chain_tops = OPS_PER_UPDATE * updates_per_wave / (chain_ms * 1e-3) / 1e12
     traffic = committed_traffic(args.fmt)
     alg_gbs = BYTES_PER_UPDATE[args.fmt] * updates_per_wave / (wave_ms * 1e-3) / 1e9
@@ -317,7 +316,7 @@ def main():
                 "launch_unit": f"wave of {main_run['groups']} concurrent group dispatches of "
                                f"{main_run['grid']} workgroups, half a sweep of every replica",
                 "wave_ms": round(wave_ms, 5), "ops_per_update": OPS_PER_UPDATE,
-                "single_chain": {"kernel_ms": round(chain_ms, 5), "workgroups": kms.get("grid"),
+                "single_chain": {"kernel_ms": round(chain_ms, 5), "workgroups": chain_run["grid"],
                                  "achieved": round(chain_tops, 2), "frac": round(chain_tops / VALU_PEAK_TOPS, 4)},
                 "hbm_view": {"algorithmic_GBs": round(alg_gbs, 1), "peak_GBs": HBM_PEAK_GBS,
                              "frac": round(alg_gbs / HBM_PEAK_GBS, 4)}}

@@ -86,11 +86,11 @@ struct I8Tile {
 static const I8Tile kI8Tiles[] = {
     {16, 16}, {32, 16}, {64, 16}, {128, 16}, {256, 16}, {16, 8},  {32, 8},   {64, 8},
     {16, 32}, {32, 32}, {64, 32}, {128, 32}, {16, 64}, {32, 64}, {64, 64}, {256, 64},
-    {0, 16},  {0, 8},   {0, 32},
+    {0, 16},  {0, 8},   {0, 32},  {0, kMaxMarch},
 };
 static const I8Tile kBpTilesM[] = {
     {16, 4}, {32, 4}, {64, 4}, {8, 4}, {4, 4}, {16, 2}, {16, 8}, {32, 8}, {8, 8}, {64, 8}, {4, 8}, {16, 16},
-    {0, 4},  {0, 2},  {0, 8},
+    {0, 4},  {0, 2},  {0, 8},  {0, kMaxMarch},
 };
 static const int kNumBpTilesM = (int)(sizeof(kBpTilesM) / sizeof(kBpTilesM[0]));
 static const int kNumI8Tiles = (int)(sizeof(kI8Tiles) / sizeof(kI8Tiles[0]));
@@ -118,7 +118,8 @@ static I8Shape i8_shape(const islf_replica_desc &d, int tile, int fmt = ISLF_SPI
     return s;
 }
 
-// fraction of thread-steps that touch a real chunk / word
+// fraction of a plane's thread slots that own a real chunk / word (the x
+// extent costs nothing: plans cut tiles by x steps)
 static double tile_efficiency(const islf_replica_desc &d, int fmt, int tile)
 {
     const double ny = d.Ly - 3;
@@ -127,20 +128,25 @@ static double tile_efficiency(const islf_replica_desc &d, int fmt, int tile)
     const I8Shape s = i8_shape(d, tile, fmt);
     const double per_plane = s.tj == 0 ? (double)ceil_div((long)ny * C, kBlock)
                                        : (double)ceil_div((long)ny, s.ty) * ceil_div(C, s.tj);
-    const double entries = (double)ceil_div(d.Lx, s.mx) * per_plane;
-    return (double)d.Lx * ny * C / (entries * kBlock * s.mx);
+    return ny * C / (per_plane * kBlock);
 }
 
+// The variant with the fewest idle thread slots among the default x extents
+// (16 planes int8, 4 bit-packed) and the linear tile over the whole x range;
+// that one wins ties: a workgroup's share of a plan is then mostly one
+// contiguous piece, with one set-up (view, tables, first loads, flush)
+// instead of one per tile.
 static int default_tile(const islf_replica_desc *d, int fmt)
 {
     double best = -1.0;
     int best_i = 0;
     for (int i = 0; i < num_tiles_of(fmt); ++i) {
-        if (fmt == ISLF_SPIN_INT8 && kI8Tiles[i].mx != 16) continue;
-        if (fmt == ISLF_SPIN_BITPACK && kBpTilesM[i].mx != 4) continue;
+        const I8Tile &t = fmt == ISLF_SPIN_INT8 ? kI8Tiles[i] : kBpTilesM[i];
+        const bool whole = t.tj_max == 0 && t.mx == kMaxMarch;
+        if (!whole && t.mx != (fmt == ISLF_SPIN_INT8 ? 16 : 4)) continue;
         const double eff = tile_efficiency(*d, fmt, i);
-        if (eff > best + 1e-9) {
-            best = eff;
+        if (eff > best + 1e-9 || (whole && eff > best - 1e-9)) {
+            best = std::max(best, eff);
             best_i = i;
         }
     }

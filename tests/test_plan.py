@@ -130,15 +130,20 @@ def test_mixed_batch_and_paper_scale(fmt):
     check_plan([islf.Replica(160, 480, 600, islf.GAPBC)], fmt, -1, 2048)
 
 
-def test_default_tile_prefers_full_lanes():
+def test_default_tile_prefers_full_lanes_then_whole_columns():
     # 477 main rows of 10 bit-packed words: a box of 10 x 25 leaves 7% of its
-    # lane-steps idle, the linear tile 2%
-    p = islf.plan_preview([islf.Replica(160, 480, 600, islf.GAPBC)], islf.BITPACK, grid=64)
-    assert p["shapes"][0][1] == 0
-    # a box that fills its lanes exactly is kept (ties go to the box)
+    # thread slots idle, a linear tile 2%; the linear tile over all 160 x
+    # planes wins the tie with the 4-plane one
+    p = islf.plan_preview([islf.Replica(160, 480, 600, islf.GAPBC)], islf.BITPACK, grid=512)
+    assert p["shapes"][0][1] == 0 and p["shapes"][0][3] == 160
+    # most workgroups then run one contiguous piece
+    assert np.mean(np.diff(p["first"])) < 1.1
+    # a box that fills its lanes exactly ties with the linear tile, which wins
     p = islf.plan_preview([islf.Replica(8, 67, 512, islf.GAPBC)], islf.INT8, grid=64)
-    tj, ty = p["shapes"][0][1], p["shapes"][0][2]
-    assert tj > 0 and tj * ty == BLOCK and 64 % tj == 0 and 64 % ty == 0
+    assert p["shapes"][0][1] == 0 and p["shapes"][0][3] == 8
+    # beyond 256 planes the whole-column tile marches at most 256 at a time
+    p = islf.plan_preview([islf.Replica(300, 6, 64, islf.GAPBC)], islf.BITPACK, grid=4)
+    assert p["shapes"][0][3] == 256 and p["items"][:, 4].max() <= 256
 
 
 def test_plan_preview_errors():
