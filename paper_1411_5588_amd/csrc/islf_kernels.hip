@@ -70,11 +70,9 @@ __device__ void flush_acc(Acc &a, long long *acc_base, uint32_t t, int slot)
 {
     __shared__ int red[4][kBlock / 64];
     int v[4] = {a.dB, a.dM, a.dM1, a.dMn};
+    // every lane of the workgroup reaches this point: full-wave DPP sums
 #pragma unroll
-    for (int k = 0; k < 4; ++k) {
-#pragma unroll
-        for (int off = 32; off > 0; off >>= 1) v[k] += __shfl_xor(v[k], off, 64);
-    }
+    for (int k = 0; k < 4; ++k) v[k] = __reduce_add_sync(~0ull, v[k]);
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     if (lane == 0) {
 #pragma unroll
