@@ -43,15 +43,23 @@ TEMPS = (2.0, 3.0, 4.0)
 H1 = 0.55
 SEED = 14115588
 
-# MI355X: 256 CUs x 4 SIMDs x 16 lanes at 2.4 GHz issue 39.3 T 32-bit VALU
-# lane-operations per second; HBM3E peak 8 TB/s.
-VALU_PEAK_TOPS = 256 * 4 * 16 * 2.4e9 / 1e12
+# MI355X: 256 CUs x 4 SIMDs at 2.4 GHz.  A SIMD issues up to two wave64
+# 32-bit VALU instructions per 4 cycles (32 lanes per clock: 78.6 T lane-ops/s,
+# the 157.3 TFLOP/s fp32 vector rate with an FMA counted twice); a 64-bit
+# integer product (multiply-hi/lo) takes a whole issue slot (39.3 T/s).  HBM3E
+# peak 8 TB/s.
+VALU32_PEAK = 256 * 4 * 32 * 2.4e9
+VALU64_PEAK = 256 * 4 * 16 * 2.4e9
 HBM_PEAK_GBS = 8000.0
 # algorithmic integer operations per spin update: Philox4x32-10 gives four
-# words for 10 rounds x (2 multiply-hi/lo + 2 three-input xor) = 40 operations,
-# i.e. 10 per update; the Metropolis test adds 7 (5 adds for the six-neighbour
-# sum, 1 compare against the tabulated threshold, 1 select of the flip).
-OPS_PER_UPDATE = 17
+# words for 10 rounds x (2 multiply-hi/lo + 2 three-input xor), i.e. 5 products
+# and 5 xors per update; the Metropolis test adds 7 (5 adds for the
+# six-neighbour sum, 1 compare against the tabulated threshold, 1 select of the
+# flip).  The ALU roofline is that mix at the two issue rates.
+OPS64, OPS32 = 5, 12
+OPS_PER_UPDATE = OPS64 + OPS32
+PEAK_UPDATES = 1.0 / (OPS64 / VALU64_PEAK + OPS32 / VALU32_PEAK)   # updates per second
+ALU_PEAK_TOPS = OPS_PER_UPDATE * PEAK_UPDATES / 1e12
 BYTES_PER_UPDATE = {"int8": 2.0, "bitpack": 0.25}   # each spin read and written once per sweep
 PROFILE_TRAFFIC = os.path.join(ROOT, "profiles", "traffic_sweep_kernel_160x480x600x3.md")
 KERNEL_SOURCE = os.path.join(ROOT, "paper_1411_5588_amd", "csrc", "islf_kernels.hip")
@@ -310,14 +318,16 @@ def main():
     chain_tops = OPS_PER_UPDATE * updates_per_wave / (chain_ms * 1e-3) / 1e12
     traffic = committed_traffic(args.fmt)
     alg_gbs = BYTES_PER_UPDATE[args.fmt] * updates_per_wave / (wave_ms * 1e-3) / 1e9
-    roofline = {"bound": "alu", "achieved": round(achieved_tops, 2), "peak": round(VALU_PEAK_TOPS, 1),
-                "unit": "T int-op/s", "frac": round(achieved_tops / VALU_PEAK_TOPS, 4), "traffic": traffic,
+    roofline = {"bound": "alu", "achieved": round(achieved_tops, 2), "peak": round(ALU_PEAK_TOPS, 1),
+                "unit": "T int-op/s", "frac": round(achieved_tops / ALU_PEAK_TOPS, 4), "traffic": traffic,
                 "kernel": "k_sweep (A and B launches)",
+                "peak_basis": f"per update {OPS64} 64-bit products at {VALU64_PEAK / 1e12:.1f} T/s + {OPS32} 32-bit "
+                              f"ops at {VALU32_PEAK / 1e12:.1f} T/s = {PEAK_UPDATES / 1e9:.0f} updates/ns",
                 "launch_unit": f"wave of {main_run['groups']} concurrent group dispatches of "
                                f"{main_run['grid']} workgroups, half a sweep of every replica",
                 "wave_ms": round(wave_ms, 5), "ops_per_update": OPS_PER_UPDATE,
                 "single_chain": {"kernel_ms": round(chain_ms, 5), "workgroups": chain_run["grid"],
-                                 "achieved": round(chain_tops, 2), "frac": round(chain_tops / VALU_PEAK_TOPS, 4)},
+                                 "achieved": round(chain_tops, 2), "frac": round(chain_tops / ALU_PEAK_TOPS, 4)},
                 "hbm_view": {"algorithmic_GBs": round(alg_gbs, 1), "peak_GBs": HBM_PEAK_GBS,
                              "frac": round(alg_gbs / HBM_PEAK_GBS, 4)}}
 

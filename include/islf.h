@@ -292,8 +292,8 @@ islf_status islf_get_groups(const islf_ctx *ctx, int32_t *groups);
 /* Workgroups per A / B launch of the batched and plain forms; the work of a
  * launch is split evenly over them.  0 (the default) means two per resident
  * slot of the sweep kernels on the device for one launch chain; concurrent
- * replica groups of the batched form together get 3/2 per slot (bit-packed)
- * or 5/2 (int8), split evenly (at least 64 per group); a nonzero value
+ * replica groups of the batched form together get 3/2 per slot, split
+ * evenly (at least 64 per group); a nonzero value
  * applies to every group's launches.  islf_get_grid reports the count of one
  * launch of the context's form (of one group's launch with several groups;
  * of the batched form for a persistent context).  Every choice computes the

@@ -575,15 +575,14 @@ static int num_groups(const islf_ctx *c)
 
 // Workgroups per A / B launch of a form: the override, else two per resident
 // slot for one launch chain.  Concurrent groups share the resident slots:
-// together they keep 3/2 workgroups per slot in flight (bit-packed, whose
-// workgroups pay more set-up) or 5/2 (int8), split evenly among the groups.
+// together they keep 3/2 workgroups per slot in flight, split evenly among
+// the groups (the tail of one group's launch is filled by the others').
 static int launch_grid(const islf_ctx *c, int exec)
 {
     if (c->grid_override) return c->grid_override;
     const int G = exec == ISLF_EXEC_BATCHED ? num_groups(c) : 1;
     if (G == 1) return c->sweep_slots;
-    const long halves = c->fmt == ISLF_SPIN_BITPACK ? 3 : 5;
-    return (int)std::max(64l, (halves * c->resident_slots + G) / (2l * G));
+    return (int)std::max(64l, (3l * c->resident_slots + G) / (2l * G));
 }
 
 // Concurrent groups of the batched form: live replicas dealt to the group
