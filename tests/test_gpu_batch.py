@@ -72,6 +72,41 @@ def test_concurrent_groups_graph_and_eager(groups, grid):
         assert np.array_equal(spins[i], o_s), i
 
 
+def test_group_and_grid_settings():
+    # automatic grouping takes min(4, live replicas); the default grid of a
+    # grouped launch is 3/2 per resident slot split over the groups (the
+    # single chain's default is two per slot); bad values are refused
+    ps = batch_params()
+    with islf.Context([islf.Replica(**p) for p in ps], spin_format=islf.BITPACK, obs_capacity=16) as ctx:
+        assert ctx.get_groups() == 4
+        ctx.set_groups(16)
+        assert ctx.get_groups() == 4
+        ctx.set_groups(1)
+        chain = ctx.get_grid()
+        resident = chain // 2
+        for g in (2, 3, 4):
+            ctx.set_groups(g)
+            assert ctx.get_groups() == g
+            assert ctx.get_grid() == max(64, (3 * resident + g) // (2 * g))
+        ctx.set_grid(100)
+        assert ctx.get_grid() == 100
+        for bad_groups in (-1, 17):
+            with pytest.raises(islf.IslfError) as e:
+                ctx.set_groups(bad_groups)
+            assert e.value.status == islf.EINVAL
+        for bad_grid in (-1, (1 << 20) + 1):
+            with pytest.raises(islf.IslfError) as e:
+                ctx.set_grid(bad_grid)
+            assert e.value.status == islf.EINVAL
+        ctx.set_grid(0)
+        ctx.set_groups(0)
+        ctx.sweep(3)
+        recs = [ctx.measure(i, 0, 3) for i in range(len(ps))]
+    for i, p in enumerate(ps):
+        _, o_rec, _ = oracle_trajectory(p, 3)
+        assert np.array_equal(recs[i], o_rec), i
+
+
 def test_alone_equals_in_mix_with_admission_and_retirement():
     ps = batch_params()
     target = ps[1]
