@@ -159,6 +159,34 @@ def layer_profile_rate(islf, torch, calls=20):
             "replica": f"{Lx}x{Ly}x{Lz} bit-packed"}
 
 
+def host_io_rate(islf, torch, fmt, chunk, ms_per_sweep):
+    """The boundary's host hand-over for one replica of the workload: a full
+    spin export (device kernel + copy into pageable host memory, int8 +-1 in
+    the host layout) and a full import, wall-clock milliseconds; and the
+    whole-job rate if every replica's spins went to the host after each graph
+    launch of `chunk` sweeps."""
+    Lx, Ly, Lz = SHAPE
+    N = Lx * Ly * Lz
+    f = {"int8": islf.INT8, "bitpack": islf.BITPACK}[fmt]
+    r = replicas(islf)[:1]
+    with islf.Context(r, spin_format=f, obs_capacity=8) as ctx:
+        s = ctx.get_spins(0)
+        t = time.perf_counter()
+        for _ in range(3):
+            s = ctx.get_spins(0)
+        get_ms = (time.perf_counter() - t) * 1e3 / 3
+    with islf.Context(r, spin_format=f, obs_capacity=8) as ctx:
+        t = time.perf_counter()
+        ctx.set_spins(0, s)
+        set_ms = (time.perf_counter() - t) * 1e3
+    n = len(TEMPS)
+    launch_ms = chunk * ms_per_sweep
+    return {"get_spins_ms": round(get_ms, 2), "set_spins_ms": round(set_ms, 2),
+            "host_GBs": round(N / (get_ms * 1e-3) / 1e9, 1),
+            "pcie_inclusive_value": round(n * N * chunk / ((launch_ms + n * get_ms) * 1e6), 2),
+            "pcie_inclusive_case": f"all {n} replicas' spins copied to the host after every {chunk} sweeps"}
+
+
 def kernel_source_hash():
     with open(KERNEL_SOURCE, "rb") as f:
         return hashlib.sha256(f.read()).hexdigest()[:16]
@@ -333,6 +361,8 @@ def main():
 
     prof = layer_profile_rate(islf, torch)
     print(f"# layer profile: {prof}", file=sys.stderr, flush=True)
+    hio = host_io_rate(islf, torch, args.fmt, main_run["sweeps_per_launch"], main_run["ms_per_sweep"])
+    print(f"# host io: {hio}", file=sys.stderr, flush=True)
 
     cpu = None if args.no_cpu else cpu_baseline(args.cpu_sweeps)
     line = {
@@ -348,6 +378,7 @@ def main():
         "forms": forms,
         "roofline": roofline,
         "layer_profile": prof,
+        "host_io": hio,
         "cpu_baseline": cpu,
     }
     print(json.dumps(line), flush=True)
