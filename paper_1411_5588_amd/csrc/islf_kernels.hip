@@ -923,9 +923,13 @@ __global__ __launch_bounds__(kBlock) void k_fold(const RepDesc *__restrict__ des
 // Persistent form: the same schedule inside one cooperative launch, with a
 // bounded two-level grid barrier in place of each launch boundary.
 // ---------------------------------------------------------------------------
+// Polls a barrier word.  Relaxed: an acquire load invalidates the XCD's L2 on
+// every poll, which evicts the lattice data of the blocks still working;
+// grid_barrier orders the data with one fence after the wait instead (a
+// relaxed load that sees the releasing increment, then an acquire fence).
 __device__ __forceinline__ unsigned long long sync_load(unsigned long long *p)
 {
-    return __hip_atomic_load(p, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
 // Waits (bounded) until *p >= target; false on time-out or a raised error.
@@ -953,7 +957,8 @@ __device__ bool grid_barrier(GridSync *sync, unsigned long long nblocks, unsigne
         const unsigned long long g = blockIdx.x / kBarrierGroup;
         const unsigned long long gsize = min((unsigned long long)kBarrierGroup, nblocks - g * kBarrierGroup);
         bool good = true;
-        __threadfence();
+        // release: this block's stores are written back before it arrives
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
         const unsigned long long old = atomicAdd(&sync->arrive[g].v, 1ull);
         if (old + 1 == k1 * gsize) {
             atomicAdd(&sync->top.v, 1ull);
@@ -962,7 +967,8 @@ __device__ bool grid_barrier(GridSync *sync, unsigned long long nblocks, unsigne
         } else {
             good = sync_wait(sync, &sync->release[g].v, k1);
         }
-        __threadfence();
+        // acquire: stale cached lines are dropped before the next phase reads
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
         ok = good ? 1 : 0;
     }
     passed += 1;
