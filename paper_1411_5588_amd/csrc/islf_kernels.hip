@@ -523,7 +523,10 @@ __device__ __forceinline__ BpStep bp_load_step(const gcu8 *base, uint32_t own, u
 }
 
 // 8 x 8 bit-matrix transpose of the 64-bit value (hi:lo): bit c of byte r
-// moves to bit r of byte c (three delta swaps).
+// moves to bit r of byte c (three delta swaps).  Kept in 64-bit form: hipcc
+// turns the swaps into 64-bit shifts, 24-bit multiplies and one 64-bit
+// product, which measured faster than a hand-written form in 32-bit shifts
+// and three-input bitwise ops.
 __device__ __forceinline__ void transpose8x8(uint32_t &lo, uint32_t &hi)
 {
     uint64_t x = ((uint64_t)hi << 32) | lo, t;
@@ -536,6 +539,56 @@ __device__ __forceinline__ void transpose8x8(uint32_t &lo, uint32_t &hi)
     lo = (uint32_t)x;
     hi = (uint32_t)(x >> 32);
 }
+
+// Shifts the reject bits (thr - 1 < r) of eight sites into two words:
+// lo = 2 lo + reject(site of t[l].x, r0[l]) and hi likewise with t[l].y and
+// r1[l], for l = 3, 2, 1, 0 (FIRST: lo and hi start from 0).  Each compare
+// writes a carry register that an add-with-carry (x + x + carry) consumes:
+// two instructions per site.  Three carry registers rotate so that each is
+// read two or more instructions after the compare writes it, the wait gfx950
+// needs between a VALU write of a scalar register and a VALU read of it.
+// VALU instructions only.
+#define ISLF_REJECT8_ASM(LO0, HI0)                                                                                     \
+    "v_cmp_lt_u32_e64 %[a], %[t3x], %[r03]\n\t"                                                                         \
+    "v_cmp_lt_u32_e64 %[b], %[t3y], %[r13]\n\t"                                                                         \
+    "v_cmp_lt_u32_e32 vcc, %[t2x], %[r02]\n\t"                                                                          \
+    "v_addc_co_u32_e64 %[lo], %[a], " LO0 ", " LO0 ", %[a]\n\t"                                                         \
+    "v_addc_co_u32_e64 %[hi], %[b], " HI0 ", " HI0 ", %[b]\n\t"                                                         \
+    "v_cmp_lt_u32_e64 %[a], %[t2y], %[r12]\n\t"                                                                         \
+    "v_addc_co_u32_e32 %[lo], vcc, %[lo], %[lo], vcc\n\t"                                                               \
+    "v_cmp_lt_u32_e64 %[b], %[t1x], %[r01]\n\t"                                                                         \
+    "v_cmp_lt_u32_e32 vcc, %[t1y], %[r11]\n\t"                                                                          \
+    "v_addc_co_u32_e64 %[hi], %[a], %[hi], %[hi], %[a]\n\t"                                                             \
+    "v_addc_co_u32_e64 %[lo], %[b], %[lo], %[lo], %[b]\n\t"                                                             \
+    "v_cmp_lt_u32_e64 %[a], %[t0x], %[r00]\n\t"                                                                         \
+    "v_addc_co_u32_e32 %[hi], vcc, %[hi], %[hi], vcc\n\t"                                                               \
+    "v_cmp_lt_u32_e64 %[b], %[t0y], %[r10]\n\t"                                                                         \
+    "v_addc_co_u32_e64 %[lo], %[a], %[lo], %[lo], %[a]\n\t"                                                             \
+    "s_nop 0\n\t"                                                                                                       \
+    "v_addc_co_u32_e64 %[hi], %[b], %[hi], %[hi], %[b]"
+#define ISLF_REJECT8_IN                                                                                                \
+    [t3x] "v"(t[3].x), [t3y] "v"(t[3].y), [t2x] "v"(t[2].x), [t2y] "v"(t[2].y), [t1x] "v"(t[1].x),                   \
+        [t1y] "v"(t[1].y), [t0x] "v"(t[0].x), [t0y] "v"(t[0].y), [r03] "v"(r0[3]), [r13] "v"(r1[3]),                  \
+        [r02] "v"(r0[2]), [r12] "v"(r1[2]), [r01] "v"(r0[1]), [r11] "v"(r1[1]), [r00] "v"(r0[0]), [r10] "v"(r1[0])
+
+template <bool FIRST>
+__device__ __forceinline__ void reject_bits8(uint32_t &lo, uint32_t &hi, const uint2 t[4], const uint32_t r0[4],
+                                             const uint32_t r1[4])
+{
+    uint64_t ca, cb;
+    if (FIRST)
+        asm(ISLF_REJECT8_ASM("0", "0")
+            : [lo] "=&v"(lo), [hi] "=&v"(hi), [a] "=&s"(ca), [b] "=&s"(cb)
+            : ISLF_REJECT8_IN
+            : "vcc");
+    else
+        asm(ISLF_REJECT8_ASM("%[lo]", "%[hi]")
+            : [lo] "+v"(lo), [hi] "+v"(hi), [a] "=&s"(ca), [b] "=&s"(cb)
+            : ISLF_REJECT8_IN
+            : "vcc");
+}
+#undef ISLF_REJECT8_ASM
+#undef ISLF_REJECT8_IN
 
 // Accept bits of the 32 sites of one word, bulk class, thresholds read from
 // the pair table for the site pairs (j, j+16).  The pair indices come from
@@ -558,29 +611,23 @@ __device__ __forceinline__ uint32_t bp_flips_pairs(uint32_t S, uint32_t b2, uint
     w[3] = __builtin_amdgcn_perm(B, A, 0x07060302u);
     transpose8x8(w[0], w[1]);
     transpose8x8(w[2], w[3]);
-    uint32_t F = 0;
-    // w[0] always holds the current iteration's pair indices; the thresholds
-    // are read before the draws so that the LDS latency overlaps Philox
+    // sites are visited from the top down (g = 3 .. 0, l = 3 .. 0), so that
+    // the shifted-in reject bits end at their site's position; the
+    // thresholds are read before the draws so that the LDS latency overlaps
+    // Philox
+    uint32_t rlo, rhi;
 #pragma unroll
-    for (int g = 0; g < 4; ++g) {
+    for (int g = 3; g >= 0; --g) {
         uint2 t[4];
 #pragma unroll
-        for (int l = 0; l < 4; ++l) t[l] = tb->pair[(w[0] >> (8 * l)) & 0xFFu];
+        for (int l = 0; l < 4; ++l) t[l] = tb->pair[(w[g] >> (8 * l)) & 0xFFu];
         uint32_t r0[4], r1[4];
         philox10(gq + 2u * (uint32_t)g, v.t, v.replica, 0u, v.key0, v.key1, r0);
         philox10(gq + 2u * (uint32_t)(g + 4), v.t, v.replica, 0u, v.key0, v.key1, r1);
-        uint32_t Fg = 0;
-#pragma unroll
-        for (int l = 0; l < 4; ++l) {
-            Fg |= (r0[l] <= t[l].x ? 1u : 0u) << l;
-            Fg |= (r1[l] <= t[l].y ? 1u : 0u) << (l + 16);
-        }
-        F |= Fg << (4 * g);
-        w[0] = w[1];
-        w[1] = w[2];
-        w[2] = w[3];
+        if (g == 3) reject_bits8<true>(rlo, rhi, t, r0, r1);
+        else reject_bits8<false>(rlo, rhi, t, r0, r1);
     }
-    return F;
+    return ~(rlo | (rhi << 16));
 }
 
 // Accept bits of the 32 sites of one word, any class: eight Philox draws
@@ -661,7 +708,10 @@ __device__ __forceinline__ void bp_march(const RepView &v, const Entry &en, int 
     uint32_t O = *(gcu32 *)(base + own_of(rw, q ^ 1));
     uint32_t xm = (x0 > 0) ? *(gcu32 *)(base + own_of(rw, q) - XB) : 0u;
     BpStep cur = bp_load_step(base, own_of(rw, q), edge_of(rw, q), RWB, XB, x0 < Lx - 1);
-    int dB = 0, dM = 0;
+    // per-thread sums over the flipped sites of the march: NF = flips, NFU =
+    // flips of up spins, A0..A2 = bit planes of a' = c (up) or 7 - c (down),
+    // c = up neighbours; KDM = sum of (6 - k) dm over the surface planes
+    int NF = 0, NFU = 0, A0 = 0, A1 = 0, A2 = 0, KDM = 0;
     for (int x = x0; x < x1; ++x) {
         const uint32_t own = own_of(rw, q);
         BpStep nxt;
@@ -678,22 +728,24 @@ __device__ __forceinline__ void bp_march(const RepView &v, const Entry &en, int 
         const uint32_t b1 = c1 ^ c2 ^ k0, b2 = (c1 & c2) | (k0 & (c1 ^ c2));
 
         const int cls = (x == 0 ? 1 : 0) + (x == Lx - 1 ? 2 : 0);
-        const int k = 6 - (x == 0) - (x == Lx - 1);
         uint32_t F;
         if (!NEVER && cls == 0) F = bp_flips_pairs(S, b2, b1, b0, gq, v, tb);
         else F = bp_flips<NEVER>(S, b2, b1, b0, gq, v, tb, cls);
         F &= vmask;
         wout[own >> 2] = S ^ F;
         const uint32_t FU = F & S;
-        const int nf = __popc(F), nfu = __popc(FU);
-        const int Sf = __popc(F & b0) + 2 * __popc(F & b1) + 4 * __popc(F & b2);
-        const int Sfu = __popc(FU & b0) + 2 * __popc(FU & b1) + 4 * __popc(FU & b2);
-        const int db = -2 * (4 * Sfu - 2 * k * nfu - 2 * Sf + k * nf);
-        const int dm = 2 * nf - 4 * nfu;
-        dB += db;
-        dM += dm;
-        if (x == 0) a.dM1 += dm;
-        if (x == Lx - 1) a.dMn += dm;
+        NF += __popc(F);
+        NFU += __popc(FU);
+        // F & ~(b ^ S): the bit planes of a' on the flipped sites
+        A0 += __popc(__builtin_amdgcn_bitop3_b32(F, b0, S, 0x90));
+        A1 += __popc(__builtin_amdgcn_bitop3_b32(F, b1, S, 0x90));
+        A2 += __popc(__builtin_amdgcn_bitop3_b32(F, b2, S, 0x90));
+        if (cls != 0) {
+            const int dm = 2 * __popc(F) - 4 * __popc(FU);
+            if (x == 0) a.dM1 += dm;
+            if (x == Lx - 1) a.dMn += dm;
+            KDM += ((x == 0) + (x == Lx - 1)) * dm;
+        }
         // the next plane: its x-1 word is this plane's other sublattice, its
         // other-sublattice word is this plane's x+1 word
         xm = O;
@@ -704,8 +756,11 @@ __device__ __forceinline__ void bp_march(const RepView &v, const Entry &en, int 
         gq ^= 1u;
         q ^= 1;
     }
-    a.dB += dB;
-    a.dM += dM;
+    // a flip of spin s = 2u - 1 with c of its k neighbours up changes B by
+    // -2 s (2c - k) = -2 (2a' - k) (up) or -2 (2a' + k - 14) (down); summed
+    // with k = 6 - (6 - k): -4 A + 16 NF - 4 NFU + KDM, A = A0 + 2 A1 + 4 A2
+    a.dB += -4 * (A0 + 2 * A1 + 4 * A2) + 16 * NF - 4 * NFU + KDM;
+    a.dM += 2 * NF - 4 * NFU;
 }
 
 // ---------------------------------------------------------------------------
