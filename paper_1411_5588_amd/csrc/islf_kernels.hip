@@ -34,12 +34,17 @@ __device__ __forceinline__ uint32_t xor3(uint32_t a, uint32_t b, uint32_t c)
 // whose halves are xored into the other counter words with the round key; the
 // key advances by the Weyl constants after each round.
 // ---------------------------------------------------------------------------
+// The first round's product of c0 = base + OFF is formed as one multiply-add,
+// M0 base + M0 OFF, which is M0 c0 whenever base + OFF < 2^32 (every counter
+// of a valid site: the group index is checked against 2^32 when a replica is
+// created); OFF = 0 is the plain generator.
+template <uint32_t OFF = 0>
 __device__ __forceinline__ void philox10(uint32_t c0, uint32_t c1, uint32_t c2, uint32_t c3,
                                          uint32_t k0, uint32_t k1, uint32_t out[4])
 {
 #pragma unroll
     for (int r = 0; r < 10; ++r) {
-        const uint64_t pa = (uint64_t)0xD2511F53u * c0;
+        const uint64_t pa = (uint64_t)0xD2511F53u * c0 + (r == 0 ? (uint64_t)0xD2511F53u * OFF : 0ull);
         const uint64_t pb = (uint64_t)0xCD9E8D57u * c2;
         const uint32_t n0 = xor3((uint32_t)(pb >> 32), c1, k0);
         const uint32_t n2 = xor3((uint32_t)(pa >> 32), c3, k1);
@@ -516,9 +521,9 @@ __device__ __forceinline__ BpStep bp_load_step(const gcu8 *base, uint32_t own, u
     BpStep n;
     n.S = *(gcu32 *)(base + own);
     n.A = *(gcu32 *)(base + edge);
-    n.yp = *(gcu32 *)(base + own + RWB);
-    n.ym = *(gcu32 *)(base + own - RWB);
-    n.xp = has_xp ? *(gcu32 *)(base + own + XB) : 0u;
+    n.yp = *(gcu32 *)(base + (own + RWB));
+    n.ym = *(gcu32 *)(base + (own - RWB));
+    n.xp = has_xp ? *(gcu32 *)(base + (own + XB)) : 0u;
     return n;
 }
 
@@ -616,17 +621,20 @@ __device__ __forceinline__ uint32_t bp_flips_pairs(uint32_t S, uint32_t b2, uint
     // thresholds are read before the draws so that the LDS latency overlaps
     // Philox
     uint32_t rlo, rhi;
-#pragma unroll
-    for (int g = 3; g >= 0; --g) {
+    auto group = [&](auto gc) {
+        constexpr int g = decltype(gc)::value;
         uint2 t[4];
 #pragma unroll
         for (int l = 0; l < 4; ++l) t[l] = tb->pair[(w[g] >> (8 * l)) & 0xFFu];
         uint32_t r0[4], r1[4];
-        philox10(gq + 2u * (uint32_t)g, v.t, v.replica, 0u, v.key0, v.key1, r0);
-        philox10(gq + 2u * (uint32_t)(g + 4), v.t, v.replica, 0u, v.key0, v.key1, r1);
-        if (g == 3) reject_bits8<true>(rlo, rhi, t, r0, r1);
-        else reject_bits8<false>(rlo, rhi, t, r0, r1);
-    }
+        philox10<2u * g>(gq, v.t, v.replica, 0u, v.key0, v.key1, r0);
+        philox10<2u * (g + 4)>(gq, v.t, v.replica, 0u, v.key0, v.key1, r1);
+        reject_bits8<g == 3>(rlo, rhi, t, r0, r1);
+    };
+    group(std::integral_constant<int, 3>{});
+    group(std::integral_constant<int, 2>{});
+    group(std::integral_constant<int, 1>{});
+    group(std::integral_constant<int, 0>{});
     return ~(rlo | (rhi << 16));
 }
 
@@ -727,10 +735,11 @@ __device__ __forceinline__ void bp_march(const RepView &v, const Entry &en, int 
         const uint32_t b0 = s1 ^ s2, k0 = s1 & s2;
         const uint32_t b1 = c1 ^ c2 ^ k0, b2 = (c1 & c2) | (k0 & (c1 ^ c2));
 
-        const int cls = (x == 0 ? 1 : 0) + (x == Lx - 1 ? 2 : 0);
+        // x is uniform across the piece: a scalar branch
+        const bool bulk = x != 0 && x != Lx - 1;
         uint32_t F;
-        if (!NEVER && cls == 0) F = bp_flips_pairs(S, b2, b1, b0, gq, v, tb);
-        else F = bp_flips<NEVER>(S, b2, b1, b0, gq, v, tb, cls);
+        if (!NEVER && bulk) F = bp_flips_pairs(S, b2, b1, b0, gq, v, tb);
+        else F = bp_flips<NEVER>(S, b2, b1, b0, gq, v, tb, (x == 0 ? 1 : 0) + (x == Lx - 1 ? 2 : 0));
         F &= vmask;
         wout[own >> 2] = S ^ F;
         const uint32_t FU = F & S;
@@ -740,7 +749,7 @@ __device__ __forceinline__ void bp_march(const RepView &v, const Entry &en, int 
         A0 += __popc(__builtin_amdgcn_bitop3_b32(F, b0, S, 0x90));
         A1 += __popc(__builtin_amdgcn_bitop3_b32(F, b1, S, 0x90));
         A2 += __popc(__builtin_amdgcn_bitop3_b32(F, b2, S, 0x90));
-        if (cls != 0) {
+        if (!bulk) {
             const int dm = 2 * __popc(F) - 4 * __popc(FU);
             if (x == 0) a.dM1 += dm;
             if (x == Lx - 1) a.dMn += dm;
