@@ -123,6 +123,20 @@ def test_every_tile_variant_gives_the_same_chain(fmt, shape):
 
 
 @pytest.mark.parametrize("fmt", FORMATS)
+@pytest.mark.parametrize("Lx", [1, 2, 3])
+def test_films_of_surface_planes(fmt, Lx):
+    # Lx = 1: both surface fields on one plane (4 neighbours); Lx = 2: every
+    # plane a surface; Lx = 3: one bulk plane between them.  Main rows
+    # (Ly = 10), a ragged int8 row and a partial bit-packed word (Lz = 70),
+    # and a bulk field H, so the surface terms of the observable changes are
+    # all exercised.
+    p = config1(Lx=Lx, Ly=10, Lz=70, ybc=O.GAPBC, beta=0.45, H=0.05, h1=0.6, hn=-0.4, replica=10 + Lx)
+    n = 15
+    s0, rec, s1, rc, t = gpu_trajectory([p], n, fmt=fmt)
+    assert_same(p, n, s0[0], rec[0], s1[0], rc[0], t[0])
+
+
+@pytest.mark.parametrize("fmt", FORMATS)
 def test_host_spins(fmt):
     p = config1(Lx=4, Ly=6, Lz=10, init=islf.INIT_HOST)
     rng = np.random.default_rng(3)
