@@ -295,10 +295,12 @@ islf_status islf_get_groups(const islf_ctx *ctx, int32_t *groups);
  * replica groups of the batched form together get 3/2 per slot, split
  * evenly (at least 64 per group); a nonzero value
  * applies to every group's launches.  islf_get_grid reports the count of one
- * launch of the context's form (of one group's launch with several groups;
- * of the batched form for a persistent context).  Every choice computes the
- * same result.  Changing it invalidates a captured graph.  Errors: EINVAL
- * (NULL context, workgroups < 0 or > 2^20). */
+ * launch of the context's form: of one group's launch with several groups;
+ * for a persistent context, the grid of its cooperative launch (set by the
+ * device, one workgroup per CU below the persistent kernel's theoretical
+ * occupancy, not by islf_set_grid).  Every choice computes the same result.
+ * Changing it invalidates a captured graph.  Errors: EINVAL (NULL context,
+ * workgroups < 0 or > 2^20). */
 islf_status islf_set_grid(islf_ctx *ctx, int32_t workgroups);
 islf_status islf_get_grid(const islf_ctx *ctx, int32_t *workgroups);
 

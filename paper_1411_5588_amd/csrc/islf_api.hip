@@ -1580,7 +1580,7 @@ extern "C" islf_status islf_get_groups(const islf_ctx *ctx, int32_t *groups)
 extern "C" islf_status islf_get_grid(const islf_ctx *ctx, int32_t *workgroups)
 {
     if (!ctx || !workgroups) return fail(ISLF_EINVAL, "NULL argument");
-    *workgroups = launch_grid(ctx, ctx->exec == ISLF_EXEC_PERSISTENT ? ISLF_EXEC_BATCHED : ctx->exec);
+    *workgroups = ctx->exec == ISLF_EXEC_PERSISTENT ? ctx->persistent_grid : launch_grid(ctx, ctx->exec);
     return ISLF_OK;
 }
 

@@ -72,6 +72,23 @@ def test_concurrent_groups_graph_and_eager(groups, grid):
         assert np.array_equal(spins[i], o_s), i
 
 
+def test_persistent_grid_is_co_resident():
+    # the cooperative launch takes one workgroup per CU below the persistent
+    # kernel's theoretical occupancy, whatever the batched grid setting
+    import torch
+    num_cu = torch.cuda.get_device_properties(0).multi_processor_count
+    ps = batch_params()
+    reps = [islf.Replica(**p) for p in ps]
+    with islf.Context(reps, spin_format=islf.BITPACK, obs_capacity=16) as ctx:
+        ctx.set_groups(1)
+        resident = ctx.get_grid() // 2
+    with islf.Context(reps, spin_format=islf.BITPACK, obs_capacity=16, exec_mode=islf.EXEC_PERSISTENT) as ctx:
+        grid = ctx.get_grid()
+        assert grid % num_cu == 0 and 0 < grid < resident + num_cu
+        ctx.set_grid(100)
+        assert ctx.get_grid() == grid
+
+
 def test_group_and_grid_settings():
     # automatic grouping takes min(4, live replicas); the default grid of a
     # grouped launch is 3/2 per resident slot split over the groups (the
