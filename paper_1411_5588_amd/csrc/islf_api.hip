@@ -430,7 +430,21 @@ static void free_plan(islf_ctx *c, Plan &p)
     p = Plan();
 }
 
-constexpr double kTailTaper = 0.2;
+// Shares of a launch are tapered by dispatch rank (later workgroups get
+// less) against the uneven progress of the workgroups resident on one CU
+// (issue goes oldest first).  Measured on the 3 x 160x480x600 workload, by
+// graph replay of the grouped batched form: bit-packed is fastest untapered
+// (+1.2% over +-20%), int8 at +-10..30% (+0.5%).
+static double tail_taper(int fmt)
+{
+    return fmt == ISLF_SPIN_BITPACK ? 0.0 : 0.1;
+}
+// a plain launch holds one replica: shorter launches, whose tails weigh more
+constexpr double kPlainTaper = 0.2;
+// the persistent launch has no second round of workgroups to fill a CU
+// whose resident workgroups finish at different times (issue goes oldest
+// first), so its shares are tapered harder: 0.3-0.4 measured best, 5% over 0.2
+constexpr double kPersistentTaper = 0.4;
 constexpr int kAutoGroups = 4;
 constexpr int kMaxStreamGroups = 16;   // concurrent replica groups of the batched form (hardware queues per process)
 
@@ -443,7 +457,7 @@ constexpr int kMaxStreamGroups = 16;   // concurrent replica groups of the batch
 // per thread over its three row stages and is never cut.  Returns the number
 // of workgroups holding slab items.
 static int partition_items(const std::vector<Entry> &slab, const std::vector<Entry> &main, int grid,
-                           std::vector<Entry> &items, std::vector<int> &first)
+                           std::vector<Entry> &items, std::vector<int> &first, double taper)
 {
     auto slab_cost = [](const Entry &e) -> long long {
         const long long tasks = 6ll * e.y0 * e.nsteps;
@@ -464,7 +478,7 @@ static int partition_items(const std::vector<Entry> &slab, const std::vector<Ent
     // cumulative cost targets: run r goes to the workgroup dispatched at rank
     // d(r) (the inverse of the kernel's XCD-contiguous mapping); later ranks
     // get smaller shares, weight 1 + a (1 - 2 u) at u = (d + 0.5) / grid
-    const double a = kTailTaper;
+    const double a = taper;
     std::vector<double> cum(grid + 1, 0.0);
     const long q = grid / 8, r8 = grid % 8;
     for (int r = 0; r < grid; ++r) {
@@ -510,11 +524,11 @@ static int partition_items(const std::vector<Entry> &slab, const std::vector<Ent
 }
 
 static islf_status build_plan(islf_ctx *c, Plan &p, const std::vector<Entry> &slab, const std::vector<Entry> &main,
-                              int grid)
+                              int grid, double taper = -1.0)
 {
     std::vector<Entry> items;
     std::vector<int> first;
-    p.slab_grid = partition_items(slab, main, grid, items, first);
+    p.slab_grid = partition_items(slab, main, grid, items, first, taper < 0.0 ? tail_taper(c->fmt) : taper);
     p.grid = (int)first.size() - 1;
     if ((long)items.size() > p.items_cap) {
         dev_free(c, p.items);
@@ -672,7 +686,7 @@ static islf_status prepare_plans(islf_ctx *c, int exec)
     if (exec == ISLF_EXEC_PERSISTENT && !c->persistent.valid) {
         std::vector<Entry> S, M;
         lists(c->live, S, M);
-        return build_plan(c, c->persistent, S, M, c->persistent_grid);
+        return build_plan(c, c->persistent, S, M, c->persistent_grid, kPersistentTaper);
     }
     if (exec == ISLF_EXEC_PLAIN) {
         if (c->plain.size() < c->reps.size()) c->plain.resize(c->reps.size());
@@ -680,7 +694,7 @@ static islf_status prepare_plans(islf_ctx *c, int exec)
             if (c->plain[r].valid) continue;
             std::vector<Entry> S, M;
             lists(std::vector<int>(1, r), S, M);
-            st = build_plan(c, c->plain[r], S, M, c->grid_override ? c->grid_override : c->sweep_slots);
+            st = build_plan(c, c->plain[r], S, M, c->grid_override ? c->grid_override : c->sweep_slots, kPlainTaper);
             if (st != ISLF_OK) return st;
         }
     }
@@ -1266,7 +1280,7 @@ extern "C" islf_status islf_plan_preview(const islf_replica_desc *descs, int32_t
     }
     std::vector<Entry> it;
     std::vector<int> fi;
-    partition_items(S, M, grid, it, fi);
+    partition_items(S, M, grid, it, fi, tail_taper(spin_format));
     *n_items = (int32_t)it.size();
     *n_first = (int32_t)fi.size();
     if ((items && (int64_t)it.size() > items_cap) || (first && (int64_t)fi.size() > first_cap))

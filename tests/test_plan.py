@@ -95,7 +95,8 @@ def check_plan(reps, fmt, tile, grid):
         k = int(np.argmax(kinds == 0)) if np.any(kinds == 0) else len(kinds)
         assert np.all(kinds[:k] == 1) and np.all(kinds[k:] == 0), b
     # balance: a main step costs 4 units, a slab tile 6 per row-stage task
-    # round of the workgroup; shares are tapered by +-20% over dispatch rank
+    # round of the workgroup; shares are tapered by at most +-20% over
+    # dispatch rank
     cost = np.zeros(len(first) - 1)
     slab_unit = 0
     for b in range(len(first) - 1):
