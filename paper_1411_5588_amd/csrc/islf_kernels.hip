@@ -384,9 +384,10 @@ __device__ __forceinline__ StepIn load_step(const RepView &v, const MarchLane &L
 // registers; the y neighbours, the z-edge bytes and the next plane are loaded
 // one step ahead (none of them is written by this thread's current step, and
 // the bytes used are not written in this phase at all).  The per-byte table
-// index 4*(cnt + 8u + 16*class) is formed with word-wide adds; a shift by 8q
-// moves the four sites of the phase to bytes 0, 2, 4, 6.  A flip adds its
-// packed (dB, dM) change to a register sum.
+// index 4*(cnt + 8u + 16*class) is formed with word-wide adds on the two
+// 32-bit halves of the chunk; a shift by 8q moves the four sites of the phase
+// to bytes 0 and 2 of each half.  A flip adds its packed (dB, dM) change to a
+// register sum.
 // The column a thread of a main tile marches: row y (2 .. Ly-2) and column j
 // (< ncol chunks or words), or false when the thread has none.  A box tile
 // is v.ty rows x v.tj columns from (en.y0, en.j0); a linear tile (v.tj = 0)
@@ -445,17 +446,35 @@ __device__ __forceinline__ void i8_march(const RepView &v, const Entry &en, int 
         StepIn nxt;
         const bool more = x + 1 < x1;
         if (more) nxt = load_step(v, L, xo + xstride, x + 1, xstride);
-        uint64_t cnt = ((Wc << 8) | (uint64_t)cur.pb) + ((Wc >> 8) | ((uint64_t)cur.nb << (8 * (L.r - 1))));
-        cnt += cur.Yp + cur.Ym;
-        cnt += Wm + cur.Wn;
-        const uint64_t clsw =
-            (x == 0 ? 0x4040404040404040ull : 0ull) + (x == Lx - 1 ? 0x8080808080808080ull : 0ull);
-        uint64_t idx = (cnt << 2) + (Wc << 5) + clsw;
-        if (RAGGED) idx = (idx & L.valid) | L.padidx;
-        idx >>= 8 * q;
+        // bytes hold 0/1 and their sums stay below 8, so no carry crosses a
+        // byte: each 32-bit half of the chunk is summed on its own
+        const uint32_t wl = (uint32_t)Wc, wh = (uint32_t)(Wc >> 32);
+        const uint32_t zml = (wl << 8) | cur.pb;
+        const uint32_t zmh = __builtin_amdgcn_alignbit(wh, wl, 24);
+        uint32_t zpl = __builtin_amdgcn_alignbit(wh, wl, 8);
+        uint32_t zph = wh >> 8;
+        if (RAGGED) {
+            const uint64_t nbw = (uint64_t)cur.nb << (8 * (L.r - 1));
+            zpl |= (uint32_t)nbw;
+            zph |= (uint32_t)(nbw >> 32);
+        } else {
+            zph |= cur.nb << 24;
+        }
+        const uint32_t cl = (zml + zpl + (uint32_t)cur.Yp) + ((uint32_t)cur.Ym + (uint32_t)Wm + (uint32_t)cur.Wn);
+        const uint32_t ch = (zmh + zph + (uint32_t)(cur.Yp >> 32)) +
+                            ((uint32_t)(cur.Ym >> 32) + (uint32_t)(Wm >> 32) + (uint32_t)(cur.Wn >> 32));
+        const uint32_t clsw = (x == 0 ? 0x40404040u : 0u) + (x == Lx - 1 ? 0x80808080u : 0u);
+        // per byte 4 (cnt + 8u) + 64 class
+        uint32_t ilo = ((cl + (wl << 3)) << 2) + clsw;
+        uint32_t ihi = ((ch + (wh << 3)) << 2) + clsw;
+        if (RAGGED) {
+            ilo = (ilo & (uint32_t)L.valid) | (uint32_t)L.padidx;
+            ihi = (ihi & (uint32_t)(L.valid >> 32)) | (uint32_t)(L.padidx >> 32);
+        }
+        ilo >>= 8 * q;
+        ihi >>= 8 * q;
         uint32_t rnd[4];
         philox10(g, v.t, v.replica, 0u, v.key0, v.key1, rnd);
-        const uint32_t ilo = (uint32_t)idx, ihi = (uint32_t)(idx >> 32);
         const uint32_t e[4] = {(ilo & 0xFFu) >> 2, (ilo >> 18) & 0x3Fu, (ihi & 0xFFu) >> 2, (ihi >> 18) & 0x3Fu};
         bool acc[4];
         int dp[4];
@@ -469,9 +488,12 @@ __device__ __forceinline__ void i8_march(const RepView &v, const Entry &en, int 
         const int step = (dp[0] + dp[1]) + (dp[2] + dp[3]);
         const uint32_t flo = (acc[0] ? 1u : 0u) | (acc[1] ? 0x10000u : 0u);
         const uint32_t fhi = (acc[2] ? 1u : 0u) | (acc[3] ? 0x10000u : 0u);
-        uint64_t flip = ((uint64_t)fhi << 32 | flo) << (8 * q);
-        if (RAGGED) flip &= L.valid;
-        *(gu64 *)((gcu8 *)v.spins + (xo + L.oc)) = Wc ^ flip;
+        uint32_t flip_l = flo << (8 * q), flip_h = fhi << (8 * q);
+        if (RAGGED) {
+            flip_l &= (uint32_t)L.valid;
+            flip_h &= (uint32_t)(L.valid >> 32);
+        }
+        *(gu64 *)((gcu8 *)v.spins + (xo + L.oc)) = Wc ^ (((uint64_t)flip_h << 32) | flip_l);
         dsum += step;
         if (x == 0) d1 += step;
         if (x == Lx - 1) dn += step;
