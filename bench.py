@@ -191,21 +191,29 @@ def host_io_rate(islf, torch, fmt, chunk, ms_per_sweep):
             "pcie_inclusive_case": f"all {n} replicas' spins copied to the host after every {chunk} sweeps"}
 
 
-def kernel_source_hash():
-    with open(KERNEL_SOURCE, "rb") as f:
-        return hashlib.sha256(f.read()).hexdigest()[:16]
+def kernel_code_hash():
+    """Hash of the kernel source with // comments, trailing blanks and empty
+    lines removed: edits to comments leave it, and the counters it guards,
+    unchanged (the source has no block comments and no "//" in strings)."""
+    lines = []
+    with open(KERNEL_SOURCE, encoding="utf-8") as f:
+        for ln in f:
+            ln = ln.split("//", 1)[0].rstrip()
+            if ln:
+                lines.append(ln)
+    return hashlib.sha256("\n".join(lines).encode()).hexdigest()[:16]
 
 
 def committed_traffic(fmt):
     """HBM bytes per launch wave of the sweep kernel (the A or B dispatches of
     all groups, half a sweep of every replica) from the committed counter
-    summary, or None when the kernel source has changed since it was taken."""
+    summary, or None when the kernel code has changed since it was taken."""
     try:
         text = open(PROFILE_TRAFFIC).read()
     except OSError:
         return None
-    m = re.search(r"kernel_source_sha256_16:\s*([0-9a-f]+)", text)
-    if not m or m.group(1) != kernel_source_hash():
+    m = re.search(r"kernel_code_sha256_16:\s*([0-9a-f]+)", text)
+    if not m or m.group(1) != kernel_code_hash():
         return None
     m = re.search(rf"traffic_bytes_per_wave\[{fmt}\]:\s*([0-9.eE+]+)", text)
     return float(m.group(1)) if m else None

@@ -531,8 +531,10 @@ __device__ __forceinline__ uint32_t spread_nibbles(uint32_t x)
 // of plane x+1 (xp) are the next step's x-1 and other-sublattice words, so
 // they stay in registers; the rest (own word, z-edge word, y neighbours,
 // plane x+2) are loaded one step ahead.  None of these words is written in
-// this phase.  Neighbour counts are bit-sliced; the 4-bit table index
-// 8u + cnt of every site is gathered into nibbles, eight sites per word.
+// this phase.  Neighbour counts are bit-sliced.  On bulk planes the 4-bit
+// table indices 8u + cnt of the site pairs (j, j+16) are gathered into bytes
+// (bp_flips_pairs); surface planes and never-accepted moves gather them into
+// nibbles and look up one site at a time (bp_flips).
 struct BpStep {
     uint32_t S, A, yp, ym, xp;
 };
