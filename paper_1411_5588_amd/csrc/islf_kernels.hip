@@ -107,8 +107,9 @@ struct TD {
 struct Tables {
     uint64_t thr[kThrEntries];
     TD td[kThrEntries];
-    // bulk class, two sites at once: entry (e1 << 4) | e0 holds the thr - 1
-    // of table indices e0 and e1 (bit-packed main tiles)
+    // bulk class, two neighbouring sites at once (bit-packed main tiles):
+    // entry k, the index bits of the two sites interleaved (even bits: the
+    // first site's e = 8u + cnt, odd bits: the second's), holds their thr - 1
     uint2 pair[256];
 };
 
@@ -121,7 +122,11 @@ __device__ __forceinline__ void load_tables(const RepDesc &d, Tables *t)
         t->td[k].dpack = d.dpack[k];
     }
     if (PAIRS)
-        for (int k = threadIdx.x; k < 256; k += blockDim.x) t->pair[k] = make_uint2(d.thr_m1[k & 15], d.thr_m1[k >> 4]);
+        for (int k = threadIdx.x; k < 256; k += blockDim.x) {
+            const int ev = (k & 1) | ((k >> 1) & 2) | ((k >> 2) & 4) | ((k >> 3) & 8);
+            const int od = ((k >> 1) & 1) | ((k >> 2) & 2) | ((k >> 3) & 4) | ((k >> 4) & 8);
+            t->pair[k] = make_uint2(d.thr_m1[ev], d.thr_m1[od]);
+        }
 }
 
 // Per-replica parameters as the update loop uses them: loaded once per
@@ -551,24 +556,6 @@ __device__ __forceinline__ BpStep bp_load_step(const gcu8 *base, uint32_t own, u
     return n;
 }
 
-// 8 x 8 bit-matrix transpose of the 64-bit value (hi:lo): bit c of byte r
-// moves to bit r of byte c (three delta swaps).  Kept in 64-bit form: hipcc
-// turns the swaps into 64-bit shifts, 24-bit multiplies and one 64-bit
-// product, which measured faster than a hand-written form in 32-bit shifts
-// and three-input bitwise ops.
-__device__ __forceinline__ void transpose8x8(uint32_t &lo, uint32_t &hi)
-{
-    uint64_t x = ((uint64_t)hi << 32) | lo, t;
-    t = (x ^ (x >> 7)) & 0x00AA00AA00AA00AAull;
-    x = x ^ t ^ (t << 7);
-    t = (x ^ (x >> 14)) & 0x0000CCCC0000CCCCull;
-    x = x ^ t ^ (t << 14);
-    t = (x ^ (x >> 28)) & 0x00000000F0F0F0F0ull;
-    x = x ^ t ^ (t << 28);
-    lo = (uint32_t)x;
-    hi = (uint32_t)(x >> 32);
-}
-
 // Shifts the reject bits (thr - 1 < r) of eight sites into two words:
 // lo = 2 lo + reject(site of t[l].x, r0[l]) and hi likewise with t[l].y and
 // r1[l], for l = 3, 2, 1, 0 (FIRST: lo and hi start from 0).  Each compare
@@ -619,27 +606,36 @@ __device__ __forceinline__ void reject_bits8(uint32_t &lo, uint32_t &hi, const u
 #undef ISLF_REJECT8_ASM
 #undef ISLF_REJECT8_IN
 
+// Transposes the 4 x 4 matrix of 2-bit fields of a word: field c of byte r
+// moves to field r of byte c (two delta swaps).
+__device__ __forceinline__ uint32_t transpose4x4x2(uint32_t x)
+{
+    uint32_t t = (x ^ (x >> 12)) & 0x0000F0F0u;
+    x = x ^ t ^ (t << 12);
+    t = (x ^ (x >> 6)) & 0x00CC00CCu;
+    return x ^ t ^ (t << 6);
+}
+
 // Accept bits of the 32 sites of one word, bulk class, thresholds read from
-// the pair table for the site pairs (j, j+16).  The pair indices come from
-// the bit planes (b0, b1, b2, S) by byte permutes and two 8 x 8 transposes:
-// byte l of w[g] is (e(4g+l+16) << 4) | e(4g+l), e = 8u + cnt.  Philox call
-// c (counter gq + 2c) draws for sites 4c .. 4c+3.
+// the pair table for the neighbouring sites (2m, 2m+1).  The pair indices
+// come from the bit planes (b0, b1, b2, S) by byte permutes (word k: the
+// planes' bytes of sites 8k' .. 8k'+7, k' = 0, 2, 1, 3 for k = 0 .. 3) and a
+// transpose of 2-bit fields in each word: byte c of word k then interleaves
+// the index bits e = 8u + cnt of sites 8k' + 2c and 8k' + 2c + 1.  Philox
+// call c (counter gq + 2c) draws for sites 4c .. 4c+3.
 __device__ __forceinline__ uint32_t bp_flips_pairs(uint32_t S, uint32_t b2, uint32_t b1, uint32_t b0, uint32_t gq,
                                                    const RepView &v, const Tables *tb)
 {
-    // rows of the two 8 x 8 blocks: bytes {b0, b1, b2, S} of sites 8k..8k+7
-    // (low word) and 8k+16..8k+23 (high word), block k = 0, 1
+    // bytes {b0, b1, b2, S} of sites 0..7, 16..23, 8..15, 24..31
     uint32_t A = __builtin_amdgcn_perm(b1, b0, 0x06020400u);
     uint32_t B = __builtin_amdgcn_perm(S, b2, 0x06020400u);
     uint32_t w[4];
-    w[0] = __builtin_amdgcn_perm(B, A, 0x05040100u);
-    w[1] = __builtin_amdgcn_perm(B, A, 0x07060302u);
+    w[0] = transpose4x4x2(__builtin_amdgcn_perm(B, A, 0x05040100u));
+    w[1] = transpose4x4x2(__builtin_amdgcn_perm(B, A, 0x07060302u));
     A = __builtin_amdgcn_perm(b1, b0, 0x07030501u);
     B = __builtin_amdgcn_perm(S, b2, 0x07030501u);
-    w[2] = __builtin_amdgcn_perm(B, A, 0x05040100u);
-    w[3] = __builtin_amdgcn_perm(B, A, 0x07060302u);
-    transpose8x8(w[0], w[1]);
-    transpose8x8(w[2], w[3]);
+    w[2] = transpose4x4x2(__builtin_amdgcn_perm(B, A, 0x05040100u));
+    w[3] = transpose4x4x2(__builtin_amdgcn_perm(B, A, 0x07060302u));
     // sites are visited from the top down (g = 3 .. 0, l = 3 .. 0), so that
     // the shifted-in reject bits end at their site's position; the
     // thresholds are read before the draws so that the LDS latency overlaps
@@ -647,9 +643,14 @@ __device__ __forceinline__ uint32_t bp_flips_pairs(uint32_t S, uint32_t b2, uint
     uint32_t rlo, rhi;
     auto group = [&](auto gc) {
         constexpr int g = decltype(gc)::value;
-        uint2 t[4];
-#pragma unroll
-        for (int l = 0; l < 4; ++l) t[l] = tb->pair[(w[g] >> (8 * l)) & 0xFFu];
+        // sites 4g .. 4g+3: bytes 2(g&1), +1 of w[g&2]; sites 4g+16 .. 4g+19:
+        // the same bytes of w[(g&2)+1]
+        constexpr int o = 16 * (g & 1);
+        const uint2 l0 = tb->pair[(w[g & 2] >> o) & 0xFFu], l1 = tb->pair[(w[g & 2] >> (o + 8)) & 0xFFu];
+        const uint2 h0 = tb->pair[(w[(g & 2) + 1] >> o) & 0xFFu], h1 = tb->pair[(w[(g & 2) + 1] >> (o + 8)) & 0xFFu];
+        // t[l]: thresholds of site 4g+l (x) and 4g+16+l (y)
+        const uint2 t[4] = {make_uint2(l0.x, h0.x), make_uint2(l0.y, h0.y), make_uint2(l1.x, h1.x),
+                            make_uint2(l1.y, h1.y)};
         uint32_t r0[4], r1[4];
         philox10<2u * g>(gq, v.t, v.replica, 0u, v.key0, v.key1, r0);
         philox10<2u * (g + 4)>(gq, v.t, v.replica, 0u, v.key0, v.key1, r1);
