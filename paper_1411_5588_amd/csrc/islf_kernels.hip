@@ -606,36 +606,24 @@ __device__ __forceinline__ void reject_bits8(uint32_t &lo, uint32_t &hi, const u
 #undef ISLF_REJECT8_ASM
 #undef ISLF_REJECT8_IN
 
-// Transposes the 4 x 4 matrix of 2-bit fields of a word: field c of byte r
-// moves to field r of byte c (two delta swaps).
-__device__ __forceinline__ uint32_t transpose4x4x2(uint32_t x)
-{
-    uint32_t t = (x ^ (x >> 12)) & 0x0000F0F0u;
-    x = x ^ t ^ (t << 12);
-    t = (x ^ (x >> 6)) & 0x00CC00CCu;
-    return x ^ t ^ (t << 6);
-}
-
 // Accept bits of the 32 sites of one word, bulk class, thresholds read from
-// the pair table for the neighbouring sites (2m, 2m+1).  The pair indices
-// come from the bit planes (b0, b1, b2, S) by byte permutes (word k: the
-// planes' bytes of sites 8k' .. 8k'+7, k' = 0, 2, 1, 3 for k = 0 .. 3) and a
-// transpose of 2-bit fields in each word: byte c of word k then interleaves
-// the index bits e = 8u + cnt of sites 8k' + 2c and 8k' + 2c + 1.  Philox
-// call c (counter gq + 2c) draws for sites 4c .. 4c+3.
+// the pair table for the neighbouring sites (2m, 2m+1).  Byte m of w[k]
+// interleaves the index bits e = 8u + cnt of sites 8m + 2k and 8m + 2k + 1:
+// its 2-bit fields are bits (2k, 2k+1) of byte m of the planes b0, b1, b2
+// and S, placed by shifts and bitfield inserts (the four fields cover every
+// bit of a byte).  Philox call c (counter gq + 2c) draws for sites
+// 4c .. 4c+3.
 __device__ __forceinline__ uint32_t bp_flips_pairs(uint32_t S, uint32_t b2, uint32_t b1, uint32_t b0, uint32_t gq,
                                                    const RepView &v, const Tables *tb)
 {
-    // bytes {b0, b1, b2, S} of sites 0..7, 16..23, 8..15, 24..31
-    uint32_t A = __builtin_amdgcn_perm(b1, b0, 0x06020400u);
-    uint32_t B = __builtin_amdgcn_perm(S, b2, 0x06020400u);
     uint32_t w[4];
-    w[0] = transpose4x4x2(__builtin_amdgcn_perm(B, A, 0x05040100u));
-    w[1] = transpose4x4x2(__builtin_amdgcn_perm(B, A, 0x07060302u));
-    A = __builtin_amdgcn_perm(b1, b0, 0x07030501u);
-    B = __builtin_amdgcn_perm(S, b2, 0x07030501u);
-    w[2] = transpose4x4x2(__builtin_amdgcn_perm(B, A, 0x05040100u));
-    w[3] = transpose4x4x2(__builtin_amdgcn_perm(B, A, 0x07060302u));
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        uint32_t acc = b0 >> (2 * k);
+        acc = __builtin_amdgcn_bitop3_b32(0x0C0C0C0Cu, k == 0 ? b1 << 2 : b1 >> (2 * k - 2), acc, 0xCA);
+        acc = __builtin_amdgcn_bitop3_b32(0x30303030u, k <= 2 ? b2 << (4 - 2 * k) : b2 >> 2, acc, 0xCA);
+        w[k] = __builtin_amdgcn_bitop3_b32(0xC0C0C0C0u, S << (6 - 2 * k), acc, 0xCA);
+    }
     // sites are visited from the top down (g = 3 .. 0, l = 3 .. 0), so that
     // the shifted-in reject bits end at their site's position; the
     // thresholds are read before the draws so that the LDS latency overlaps
@@ -643,11 +631,11 @@ __device__ __forceinline__ uint32_t bp_flips_pairs(uint32_t S, uint32_t b2, uint
     uint32_t rlo, rhi;
     auto group = [&](auto gc) {
         constexpr int g = decltype(gc)::value;
-        // sites 4g .. 4g+3: bytes 2(g&1), +1 of w[g&2]; sites 4g+16 .. 4g+19:
-        // the same bytes of w[(g&2)+1]
-        constexpr int o = 16 * (g & 1);
-        const uint2 l0 = tb->pair[(w[g & 2] >> o) & 0xFFu], l1 = tb->pair[(w[g & 2] >> (o + 8)) & 0xFFu];
-        const uint2 h0 = tb->pair[(w[(g & 2) + 1] >> o) & 0xFFu], h1 = tb->pair[(w[(g & 2) + 1] >> (o + 8)) & 0xFFu];
+        // sites 4g .. 4g+3: byte g/2 of w[2(g&1)] and w[2(g&1)+1]; sites
+        // 4g+16 .. 4g+19: byte 2 + g/2 of the same words
+        constexpr int k = 2 * (g & 1), lo = 8 * (g >> 1), hi = lo + 16;
+        const uint2 l0 = tb->pair[(w[k] >> lo) & 0xFFu], l1 = tb->pair[(w[k + 1] >> lo) & 0xFFu];
+        const uint2 h0 = tb->pair[(w[k] >> hi) & 0xFFu], h1 = tb->pair[(w[k + 1] >> hi) & 0xFFu];
         // t[l]: thresholds of site 4g+l (x) and 4g+16+l (y)
         const uint2 t[4] = {make_uint2(l0.x, h0.x), make_uint2(l0.y, h0.y), make_uint2(l1.x, h1.x),
                             make_uint2(l1.y, h1.y)};
