@@ -445,7 +445,10 @@ __device__ __forceinline__ void i8_march(const RepView &v, const Entry &en, int 
     uint64_t Wc = ld64(v.spins, xo + L.oc);
     uint64_t Wm = (x0 > 0) ? ld64(v.spins, xo - xstride + L.oc) : 0ull;
     StepIn cur = load_step(v, L, xo, x0, xstride);
-    int dsum = 0, d1 = 0, dn = 0;
+    // the surface planes x = 0 and Lx-1 can only be the first and last of
+    // the march: their sums are the first and last steps' (no per-step test)
+    int dsum = 0, dfirst = 0, dlast = 0;
+    bool first = true;
     for (int x = x0; x < x1; ++x) {
         // next step's neighbours first: independent of this step's result
         StepIn nxt;
@@ -480,13 +483,16 @@ __device__ __forceinline__ void i8_march(const RepView &v, const Entry &en, int 
         ihi >>= 8 * q;
         uint32_t rnd[4];
         philox10(g, v.t, v.replica, 0u, v.key0, v.key1, rnd);
-        const uint32_t e[4] = {(ilo & 0xFFu) >> 2, (ilo >> 18) & 0x3Fu, (ihi & 0xFFu) >> 2, (ihi >> 18) & 0x3Fu};
+        // a site's byte is 4e (e: table index) and both tables hold 8-byte
+        // entries, so the byte times 2 is the entry's byte offset
+        const uint32_t off[4] = {2u * (ilo & 0xFFu), 2u * ((ilo >> 16) & 0xFFu), 2u * (ihi & 0xFFu),
+                                 2u * ((ihi >> 16) & 0xFFu)};
         bool acc[4];
         int dp[4];
 #pragma unroll
         for (int l = 0; l < 4; ++l) {
-            const TD t = tb->td[e[l]];
-            if (NEVER) acc[l] = (uint64_t)rnd[l] < tb->thr[e[l]];
+            const TD t = *(const TD *)((const char *)tb->td + off[l]);
+            if (NEVER) acc[l] = (uint64_t)rnd[l] < *(const uint64_t *)((const char *)tb->thr + off[l]);
             else acc[l] = rnd[l] <= t.thr_m1;
             dp[l] = acc[l] ? t.dpack : 0;
         }
@@ -500,8 +506,9 @@ __device__ __forceinline__ void i8_march(const RepView &v, const Entry &en, int 
         }
         *(gu64 *)((gcu8 *)v.spins + (xo + L.oc)) = Wc ^ (((uint64_t)flip_h << 32) | flip_l);
         dsum += step;
-        if (x == 0) d1 += step;
-        if (x == Lx - 1) dn += step;
+        if (first) dfirst = step;
+        first = false;
+        dlast = step;
         Wm = Wc;
         Wc = cur.Wn;
         if (more) cur = nxt;
@@ -514,6 +521,7 @@ __device__ __forceinline__ void i8_march(const RepView &v, const Entry &en, int 
     const int dB = (int)(int16_t)(dsum & 0xFFFF), dM = (dsum - dB) >> 16;
     a.dB += dB;
     a.dM += dM;
+    const int d1 = x0 == 0 ? dfirst : 0, dn = x1 == Lx ? dlast : 0;
     const int dB1 = (int)(int16_t)(d1 & 0xFFFF), dBn = (int)(int16_t)(dn & 0xFFFF);
     a.dM1 += (d1 - dB1) >> 16;
     a.dMn += (dn - dBn) >> 16;
