@@ -27,8 +27,8 @@ const void *persistent_kernel(int fmt);
 hipError_t launch_persistent(int fmt, const RepDesc *descs, RepState *st, const Entry *items, const int *first,
                              const int *reps, int nreps, uint32_t nsweeps, GridSync *sync, int grid, hipStream_t s);
 hipError_t launch_init(int fmt, const RepDesc *descs, int rep, int mode, const int8_t *host, hipStream_t s);
-hipError_t launch_export(const RepDesc *descs, int rep, int8_t *out, hipStream_t s);
-hipError_t launch_recompute(const RepDesc *descs, int rep, const int8_t *spins, unsigned long long *out,
+hipError_t launch_export(const RepDesc *descs, int rep, long rows, int8_t *out, hipStream_t s);
+hipError_t launch_recompute(const RepDesc *descs, int rep, long rows, const int8_t *spins, unsigned long long *out,
                             hipStream_t s);
 hipError_t launch_set_state(RepState *st, int rep, const unsigned long long *obs, uint32_t t, hipStream_t s);
 hipError_t launch_layer_profile(const RepDesc *descs, int rep, long rows, long words_per_row, int32_t *out,
@@ -711,8 +711,9 @@ static islf_status init_replica(islf_ctx *c, int i, int mode, const int8_t *host
     const size_t N = (size_t)R.desc.Lx * R.desc.Ly * R.desc.Lz;
     int8_t *tmp = (int8_t *)dev_alloc(c, N);
     if (!tmp) return fail(ISLF_ENOMEM, "cannot allocate %zu bytes of staging", N);
-    hipError_t e = launch_export(c->d_desc, i, tmp, c->stream);
-    if (e == hipSuccess) e = launch_recompute(c->d_desc, i, tmp, c->d_scratch, c->stream);
+    hipError_t e = launch_export(c->d_desc, i, (long)R.desc.Lx * R.desc.Ly, tmp, c->stream);
+    if (e == hipSuccess)
+        e = launch_recompute(c->d_desc, i, (long)R.desc.Lx * R.desc.Ly, tmp, c->d_scratch, c->stream);
     if (e == hipSuccess) e = launch_set_state(c->d_state, i, c->d_scratch, 0u, c->stream);
     if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
     dev_free(c, tmp);
@@ -948,7 +949,7 @@ extern "C" islf_status islf_get_spins(islf_ctx *ctx, int32_t rep, int8_t *host, 
     if (!host || n != N) return fail(ISLF_EINVAL, "expected %zu spins, got %zu", N, n);
     int8_t *tmp = (int8_t *)dev_alloc(ctx, N);
     if (!tmp) return fail(ISLF_ENOMEM, "cannot allocate staging");
-    hipError_t e = launch_export(ctx->d_desc, rep, tmp, ctx->stream);
+    hipError_t e = launch_export(ctx->d_desc, rep, (long)R.desc.Lx * R.desc.Ly, tmp, ctx->stream);
     if (e == hipSuccess) e = hipMemcpyAsync(host, tmp, N, hipMemcpyDeviceToHost, ctx->stream);
     if (e == hipSuccess) e = hipStreamSynchronize(ctx->stream);
     dev_free(ctx, tmp);
@@ -1161,8 +1162,9 @@ extern "C" islf_status islf_recompute(islf_ctx *ctx, int32_t rep, islf_obs *out)
     int8_t *tmp = (int8_t *)dev_alloc(ctx, N);
     if (!tmp) return fail(ISLF_ENOMEM, "cannot allocate staging");
     unsigned long long h[4];
-    hipError_t e = launch_export(ctx->d_desc, rep, tmp, ctx->stream);
-    if (e == hipSuccess) e = launch_recompute(ctx->d_desc, rep, tmp, ctx->d_scratch, ctx->stream);
+    hipError_t e = launch_export(ctx->d_desc, rep, (long)R.desc.Lx * R.desc.Ly, tmp, ctx->stream);
+    if (e == hipSuccess)
+        e = launch_recompute(ctx->d_desc, rep, (long)R.desc.Lx * R.desc.Ly, tmp, ctx->d_scratch, ctx->stream);
     if (e == hipSuccess) e = hipMemcpyAsync(h, ctx->d_scratch, sizeof h, hipMemcpyDeviceToHost, ctx->stream);
     if (e == hipSuccess) e = hipStreamSynchronize(ctx->stream);
     dev_free(ctx, tmp);

@@ -1156,18 +1156,18 @@ __global__ void k_init_bp(const RepDesc *__restrict__ descs, int rep, int mode, 
 __global__ void k_export(const RepDesc *__restrict__ descs, int rep, int8_t *__restrict__ out)
 {
     const RepDesc &d = descs[rep];
-    const long N = (long)d.Lx * d.Ly * d.Lz;
-    for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < N; i += (long)gridDim.x * blockDim.x) {
-        const long row = i / d.Lz;
-        const int z = (int)(i - row * d.Lz);
-        uint32_t u;
+    const int Lz = d.Lz;
+    // a workgroup takes whole rows (x, y); the lanes run along z
+    for (int r = blockIdx.x; r < d.Lx * d.Ly; r += gridDim.x) {
+        int8_t *o = out + (size_t)r * (size_t)Lz;
         if (d.fmt == ISLF_SPIN_INT8) {
-            u = d.spins[(size_t)row * d.Lzp + z];
+            const uint8_t *src = d.spins + (size_t)r * d.Lzp;
+            for (int z = threadIdx.x; z < Lz; z += blockDim.x) o[z] = src[z] ? (int8_t)1 : (int8_t)-1;
         } else {
-            const uint32_t *sub = (const uint32_t *)d.spins + (size_t)row * 2 * d.Wq + (size_t)(z & 1) * d.Wq;
-            u = bp_bit(sub, z >> 1);
+            const uint32_t *row = (const uint32_t *)d.spins + (size_t)r * 2 * d.Wq;
+            for (int z = threadIdx.x; z < Lz; z += blockDim.x)
+                o[z] = bp_bit(row + (size_t)(z & 1) * d.Wq, z >> 1) ? (int8_t)1 : (int8_t)-1;
         }
-        out[i] = u ? (int8_t)1 : (int8_t)-1;
     }
 }
 
@@ -1180,26 +1180,50 @@ __global__ void k_recompute(const RepDesc *__restrict__ descs, int rep, const in
 {
     const RepDesc &d = descs[rep];
     const int Lx = d.Lx, Ly = d.Ly, Lz = d.Lz;
-    const long N = (long)Lx * Ly * Lz;
-    long long B = 0, M = 0, M1 = 0, Mn = 0;
-    for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < N; i += (long)gridDim.x * blockDim.x) {
-        const int z = (int)(i % Lz);
-        const long row = i / Lz;
-        const int y = (int)(row % Ly);
-        const int x = (int)(row / Ly);
-        const int si = s[i];
-        if (x < Lx - 1) B += si * s[i + (long)Ly * Lz];
-        B += si * s[row * Lz + (z + 1 == Lz ? 0 : z + 1)];
-        if (y < Ly - 1) {
-            B += si * s[i + Lz];
-        } else {
-            const int xs = d.seam_reflect ? Lx - 1 - x : x;
-            const int sg = d.seam_invert ? -1 : 1;
-            B += sg * si * s[((long)xs * Ly) * Lz + z];
+    const uint32_t plane = (uint32_t)Ly * (uint32_t)Lz;
+    const int sg = d.seam_invert ? -1 : 1;
+    // a workgroup takes whole rows (x, y), four at a time so that each lane
+    // has the loads of four rows in flight: x and y are uniform, the lanes
+    // run along z (coalesced), and offsets fit 32 bits (a replica is below
+    // 4 GiB)
+    int B = 0, M = 0, M1 = 0, Mn = 0;
+    const int rows = Lx * Ly;
+    for (int r0 = 4 * (int)blockIdx.x; r0 < rows; r0 += 4 * (int)gridDim.x) {
+        // per row (uniform): offset, y-neighbour row offset and sign, x+1 plane
+        uint32_t ro[4], yo[4];
+        int ys[4], xp[4], ok[4];
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            const int r = min(r0 + k, rows - 1);
+            const int x = r / Ly, y = r - x * Ly;
+            ok[k] = r0 + k < rows;
+            ro[k] = (uint32_t)r * (uint32_t)Lz;
+            yo[k] = y < Ly - 1 ? ro[k] + (uint32_t)Lz : (uint32_t)((d.seam_reflect ? Lx - 1 - x : x) * Ly) * Lz;
+            ys[k] = y < Ly - 1 ? 1 : sg;
+            xp[k] = x < Lx - 1;
         }
-        M += si;
-        if (x == 0) M1 += si;
-        if (x == Lx - 1) Mn += si;
+        int b[4] = {0, 0, 0, 0}, m[4] = {0, 0, 0, 0};
+        for (int z = threadIdx.x; z < Lz; z += blockDim.x) {
+            const int zn = z + 1 == Lz ? 0 : z + 1;
+#pragma unroll
+            for (int k = 0; k < 4; ++k) {
+                if (!ok[k]) break;
+                const int si = s[ro[k] + z];
+                int bb = si * s[ro[k] + zn] + ys[k] * si * s[yo[k] + z];
+                if (xp[k]) bb += si * s[ro[k] + plane + z];
+                b[k] += bb;
+                m[k] += si;
+            }
+        }
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            if (!ok[k]) break;
+            const int x = (r0 + k) / Ly;
+            B += b[k];
+            M += m[k];
+            if (x == 0) M1 += m[k];
+            if (x == Lx - 1) Mn += m[k];
+        }
     }
     long long v[4] = {B, M, M1, Mn};
     __shared__ long long red[4][kBlock / 64];
@@ -1448,17 +1472,21 @@ hipError_t launch_init(int fmt, const RepDesc *descs, int rep, int mode, const i
     return hipGetLastError();
 }
 
-hipError_t launch_export(const RepDesc *descs, int rep, int8_t *out, hipStream_t s)
+hipError_t launch_export(const RepDesc *descs, int rep, long rows, int8_t *out, hipStream_t s)
 {
-    hipLaunchKernelGGL(k_export, dim3(1024), dim3(kBlock), 0, s, descs, rep, out);
+    const unsigned grid = (unsigned)std::max(1L, std::min(rows, 1L << 20));
+    hipLaunchKernelGGL(k_export, dim3(grid), dim3(kBlock), 0, s, descs, rep, out);
     return hipGetLastError();
 }
 
-hipError_t launch_recompute(const RepDesc *descs, int rep, const int8_t *spins, unsigned long long *out,
-                            hipStream_t s)
+hipError_t launch_recompute(const RepDesc *descs, int rep, long rows, const int8_t *spins,
+                            unsigned long long *out, hipStream_t s)
 {
     hipLaunchKernelGGL(k_zero_u64, dim3(1), dim3(64), 0, s, out, 4L);
-    hipLaunchKernelGGL(k_recompute, dim3(1024), dim3(kBlock), 0, s, descs, rep, spins, out);
+    // at most 1024 workgroups: each ends with four atomics on the same four
+    // words, which serialise when there are many more
+    const unsigned grid = (unsigned)std::max(1L, std::min((rows + 3) / 4, 1024L));
+    hipLaunchKernelGGL(k_recompute, dim3(grid), dim3(kBlock), 0, s, descs, rep, spins, out);
     return hipGetLastError();
 }
 
