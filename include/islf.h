@@ -283,7 +283,7 @@ islf_status islf_layer_profile_add(islf_ctx *ctx, int32_t rep, int64_t *dev_acc)
  * context owns, forked from and joined back to the context's stream, also
  * inside a captured graph), so that the tail of one group's launch overlaps
  * the launches of the others.  Replicas are independent, so the results are
- * the same for every choice.  0 (the default) means min(4, live replicas);
+ * the same for every choice.  0 (the default) means min(3, live replicas);
  * 1 gives one launch chain over all replicas.  Changing it invalidates a
  * captured graph.  Errors: EINVAL (NULL context, groups < 0 or > 16). */
 islf_status islf_set_groups(islf_ctx *ctx, int32_t groups);

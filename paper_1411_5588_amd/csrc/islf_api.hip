@@ -445,7 +445,10 @@ constexpr double kPlainTaper = 0.2;
 // whose resident workgroups finish at different times (issue goes oldest
 // first), so its shares are tapered harder: 0.3-0.4 measured best, 5% over 0.2
 constexpr double kPersistentTaper = 0.4;
-constexpr int kAutoGroups = 4;
+// three concurrent groups: measured as fast as two and faster than four on
+// every batch tried (3 x 160x480x600, 64 x 40x120x120, 96 uneven replicas);
+// four group streams can share one of the process's four hardware queues
+constexpr int kAutoGroups = 3;
 constexpr int kMaxStreamGroups = 16;   // concurrent replica groups of the batched form (hardware queues per process)
 
 // Splits the work into about `grid` runs of equal cost, one per workgroup:

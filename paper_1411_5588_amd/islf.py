@@ -332,7 +332,7 @@ class Context:
         _check(lib().islf_set_grid(self._h, workgroups))
 
     def set_groups(self, groups: int):
-        """Concurrent replica groups of the batched form (0 = min(4, live replicas))."""
+        """Concurrent replica groups of the batched form (0 = min(3, live replicas))."""
         _check(lib().islf_set_groups(self._h, groups))
 
     def get_groups(self) -> int:

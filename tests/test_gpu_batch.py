@@ -90,12 +90,12 @@ def test_persistent_grid_is_co_resident():
 
 
 def test_group_and_grid_settings():
-    # automatic grouping takes min(4, live replicas); the default grid of a
+    # automatic grouping takes min(3, live replicas); the default grid of a
     # grouped launch is 3/2 per resident slot split over the groups (the
     # single chain's default is two per slot); bad values are refused
     ps = batch_params()
     with islf.Context([islf.Replica(**p) for p in ps], spin_format=islf.BITPACK, obs_capacity=16) as ctx:
-        assert ctx.get_groups() == 4
+        assert ctx.get_groups() == 3
         ctx.set_groups(16)
         assert ctx.get_groups() == 4
         ctx.set_groups(1)
