@@ -177,16 +177,50 @@ typedef __attribute__((address_space(1))) const uint32_t gcu32;
 typedef __attribute__((address_space(1))) const uint64_t gcu64;
 typedef __attribute__((address_space(1))) uint64_t gu64;
 typedef __attribute__((address_space(1))) uint32_t gu32;
+typedef __attribute__((address_space(1))) uint8_t gu8;
 
+// Lattice accesses.  COH (the persistent kernel) makes them relaxed
+// device-scope atomics, which the compiler marks device-coherent: stores
+// write through the XCD's L2 and loads do not use a stale copy in it, so the
+// L2 holds no dirty lattice lines when the grid barrier writes it back and
+// loses no data the next phase needs when the barrier invalidates it.
+template <bool COH>
 __device__ __forceinline__ uint64_t ld64(const uint8_t *base, uint32_t off)
 {
-    return *(gcu64 *)((gcu8 *)base + off);
+    gu64 *p = (gu64 *)((gcu8 *)base + off);
+    if (COH) return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    return *p;
 }
+template <bool COH>
+__device__ __forceinline__ uint32_t ld32(const uint8_t *base, uint32_t off)
+{
+    gu32 *p = (gu32 *)((gcu8 *)base + off);
+    if (COH) return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    return *p;
+}
+template <bool COH>
 __device__ __forceinline__ uint64_t ld8(const uint8_t *base, uint32_t off)
 {
-    return *((gcu8 *)base + off);
+    gu8 *p = (gu8 *)((gcu8 *)base + off);
+    if (COH) return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    return *p;
+}
+template <bool COH>
+__device__ __forceinline__ void st64(uint8_t *base, uint32_t off, uint64_t v)
+{
+    gu64 *p = (gu64 *)((gcu8 *)base + off);
+    if (COH) __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    else *p = v;
+}
+template <bool COH>
+__device__ __forceinline__ void st32(uint8_t *base, uint32_t off, uint32_t v)
+{
+    gu32 *p = (gu32 *)((gcu8 *)base + off);
+    if (COH) __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    else *p = v;
 }
 
+template <bool COH>
 __device__ __forceinline__ void i8_update_chunk(const RepView &v, int x, int y, int j, int parity,
                                                 const uint64_t *sthr, Acc &a)
 {
@@ -217,13 +251,13 @@ __device__ __forceinline__ void i8_update_chunk(const RepView &v, int x, int y, 
     const uint32_t oprev = (j > 0) ? off - 1u : rowoff + (uint32_t)(Lz - 1);
     const uint32_t onext = last ? rowoff : off + 8u;
 
-    const uint64_t W = ld64(sp, off);
-    const uint64_t Yp = ld64(sp, rp * Lzp + jo);
-    const uint64_t Ym = ld64(sp, rm * Lzp + jo);
-    const uint64_t Xm = ld64(sp, oxm);
-    const uint64_t Xp = ld64(sp, oxp);
-    const uint64_t prev = ld8(sp, oprev);
-    const uint64_t next = ld8(sp, onext);
+    const uint64_t W = ld64<COH>(sp, off);
+    const uint64_t Yp = ld64<COH>(sp, rp * Lzp + jo);
+    const uint64_t Ym = ld64<COH>(sp, rm * Lzp + jo);
+    const uint64_t Xm = ld64<COH>(sp, oxm);
+    const uint64_t Xp = ld64<COH>(sp, oxp);
+    const uint64_t prev = ld8<COH>(sp, oprev);
+    const uint64_t next = ld8<COH>(sp, onext);
 
     uint64_t cnt = ((W << 8) | prev) + ((W >> 8) | (next << (8 * (r - 1))));
     cnt += (Yp ^ inv_p) + (Ym ^ inv_m);
@@ -249,7 +283,7 @@ __device__ __forceinline__ void i8_update_chunk(const RepView &v, int x, int y, 
     // sites past the end of a short last chunk are padding
     const uint64_t valid = (r == 8) ? ~0ull : ((1ull << (8 * r)) - 1ull);
     flip &= valid;
-    *(gu64 *)((gcu8 *)sp + off) = W ^ flip;
+    st64<COH>(sp, off, W ^ flip);
 
     // dB = -2 sum_f s n with s = 2u-1, n = 2 cnt - k;  dM = sum_f (2 - 4u)
     const uint64_t fu = flip & W;
@@ -272,6 +306,7 @@ __device__ __forceinline__ uint32_t bp_bit(const uint32_t *sub, int i)
     return (sub[i >> 5] >> (i & 31)) & 1u;
 }
 
+template <bool COH>
 __device__ __forceinline__ void bp_update_word(const RepView &v, int x, int y, int w, int parity,
                                                const uint64_t *sthr, Acc &a)
 {
@@ -279,27 +314,28 @@ __device__ __forceinline__ void bp_update_word(const RepView &v, int x, int y, i
     const int nbits = v.Lz >> 1;
     const uint32_t RW = 2u * (uint32_t)Wq;
     const uint32_t row = (uint32_t)x * (uint32_t)Ly + (uint32_t)y;
-    uint32_t *words = (uint32_t *)v.spins;
+    auto word = [&](uint32_t i) { return ld32<COH>(v.spins, 4u * i); };
     const int q = (parity + x + y) & 1;
     const uint32_t own = row * RW + (uint32_t)(q * Wq);
     const uint32_t oth = row * RW + (uint32_t)((q ^ 1) * Wq);
     const int nb_here = min(32, nbits - 32 * w);
     const uint32_t vmask = nb_here >= 32 ? 0xFFFFFFFFu : ((1u << nb_here) - 1u);
 
-    const uint32_t S = words[own + w];
+    const uint32_t S = word(own + w);
     uint32_t zm, zp;
     if (q == 0) {
         // z = 2i: z+1 is odd index i, z-1 is odd index i-1
-        const uint32_t O = words[oth + w];
+        const uint32_t O = word(oth + w);
         zp = O;
-        const uint32_t carry = (w > 0) ? (words[oth + w - 1] >> 31) : bp_bit(words + oth, nbits - 1);
+        const uint32_t carry = (w > 0) ? (word(oth + w - 1) >> 31)
+                                       : (word(oth + ((nbits - 1) >> 5)) >> ((nbits - 1) & 31)) & 1u;
         zm = (O << 1) | carry;
     } else {
         // z = 2i+1: z-1 is even index i, z+1 is even index i+1
-        const uint32_t E = words[oth + w];
+        const uint32_t E = word(oth + w);
         zm = E;
         const bool lastw = (w == Wq - 1);
-        const uint32_t inb = words[oth + (lastw ? 0 : w + 1)] & 1u;
+        const uint32_t inb = word(oth + (lastw ? 0 : w + 1)) & 1u;
         zp = (E >> 1) | (inb << (lastw ? (nb_here - 1) : 31));
     }
 
@@ -307,13 +343,13 @@ __device__ __forceinline__ void bp_update_word(const RepView &v, int x, int y, i
     const uint32_t seam_mask = v.seam_invert ? 0xFFFFFFFFu : 0u;
     const uint32_t qo = (uint32_t)(q * Wq + w);
     uint32_t yp, ym;
-    if (y < Ly - 1) yp = words[(row + 1) * RW + qo];
-    else yp = words[(xs * (uint32_t)Ly) * RW + qo] ^ seam_mask;
-    if (y > 0) ym = words[(row - 1) * RW + qo];
-    else ym = words[(xs * (uint32_t)Ly + (uint32_t)(Ly - 1)) * RW + qo] ^ seam_mask;
+    if (y < Ly - 1) yp = word((row + 1) * RW + qo);
+    else yp = word((xs * (uint32_t)Ly) * RW + qo) ^ seam_mask;
+    if (y > 0) ym = word((row - 1) * RW + qo);
+    else ym = word((xs * (uint32_t)Ly + (uint32_t)(Ly - 1)) * RW + qo) ^ seam_mask;
     const uint32_t xstride = (uint32_t)Ly * RW;
-    const uint32_t xm = (x > 0) ? words[own + w - xstride] : 0u;
-    const uint32_t xp = (x < Lx - 1) ? words[own + w + xstride] : 0u;
+    const uint32_t xm = (x > 0) ? word(own + w - xstride) : 0u;
+    const uint32_t xp = (x < Lx - 1) ? word(own + w + xstride) : 0u;
 
     // bit-sliced count of the six neighbour bits
     const uint32_t s1 = zm ^ zp ^ ym, c1 = (zm & zp) | (ym & (zm ^ zp));
@@ -341,7 +377,7 @@ __device__ __forceinline__ void bp_update_word(const RepView &v, int x, int y, i
         }
     }
     F &= vmask;
-    words[own + w] = S ^ F;
+    st32<COH>(v.spins, 4u * (own + w), S ^ F);
 
     const uint32_t FU = F & S;
     const int nf = __popc(F), nfu = __popc(FU);
@@ -370,15 +406,16 @@ struct StepIn {
 };
 
 // xo: byte offset of plane x in the replica's spin array
+template <bool COH>
 __device__ __forceinline__ StepIn load_step(const RepView &v, const MarchLane &L, uint32_t xo, int x,
                                             uint32_t xstride)
 {
     StepIn in;
-    in.Wn = (x + 1 < v.Lx) ? ld64(v.spins, xo + xstride + L.oc) : 0ull;
-    in.Yp = ld64(v.spins, xo + L.oyp);
-    in.Ym = ld64(v.spins, xo + L.oym);
-    in.pb = (uint32_t)ld8(v.spins, xo + L.oprev);
-    in.nb = (uint32_t)ld8(v.spins, xo + L.onext);
+    in.Wn = (x + 1 < v.Lx) ? ld64<COH>(v.spins, xo + xstride + L.oc) : 0ull;
+    in.Yp = ld64<COH>(v.spins, xo + L.oyp);
+    in.Ym = ld64<COH>(v.spins, xo + L.oym);
+    in.pb = (uint32_t)ld8<COH>(v.spins, xo + L.oprev);
+    in.nb = (uint32_t)ld8<COH>(v.spins, xo + L.onext);
     return in;
 }
 
@@ -412,7 +449,7 @@ __device__ __forceinline__ bool main_column(const RepView &v, const Entry &en, i
     return lin < en.j0;
 }
 
-template <bool NEVER, bool RAGGED>
+template <bool NEVER, bool RAGGED, bool COH>
 __device__ __forceinline__ void i8_march(const RepView &v, const Entry &en, int k_lo, int k_hi, int parity,
                                          const Tables *tb, Acc &a)
 {
@@ -442,9 +479,9 @@ __device__ __forceinline__ void i8_march(const RepView &v, const Entry &en, int 
     int q = (parity + x0 + y) & 1;
     uint32_t g = ((((uint32_t)x0 * (uint32_t)Ly + (uint32_t)y) * (uint32_t)C + (uint32_t)j) << 1) | (uint32_t)q;
 
-    uint64_t Wc = ld64(v.spins, xo + L.oc);
-    uint64_t Wm = (x0 > 0) ? ld64(v.spins, xo - xstride + L.oc) : 0ull;
-    StepIn cur = load_step(v, L, xo, x0, xstride);
+    uint64_t Wc = ld64<COH>(v.spins, xo + L.oc);
+    uint64_t Wm = (x0 > 0) ? ld64<COH>(v.spins, xo - xstride + L.oc) : 0ull;
+    StepIn cur = load_step<COH>(v, L, xo, x0, xstride);
     // the surface planes x = 0 and Lx-1 can only be the first and last of
     // the march: their sums are the first and last steps' (no per-step test)
     int dsum = 0, dfirst = 0, dlast = 0;
@@ -453,7 +490,7 @@ __device__ __forceinline__ void i8_march(const RepView &v, const Entry &en, int 
         // next step's neighbours first: independent of this step's result
         StepIn nxt;
         const bool more = x + 1 < x1;
-        if (more) nxt = load_step(v, L, xo + xstride, x + 1, xstride);
+        if (more) nxt = load_step<COH>(v, L, xo + xstride, x + 1, xstride);
         // bytes hold 0/1 and their sums stay below 8, so no carry crosses a
         // byte: each 32-bit half of the chunk is summed on its own
         const uint32_t wl = (uint32_t)Wc, wh = (uint32_t)(Wc >> 32);
@@ -504,7 +541,7 @@ __device__ __forceinline__ void i8_march(const RepView &v, const Entry &en, int 
             flip_l &= (uint32_t)L.valid;
             flip_h &= (uint32_t)(L.valid >> 32);
         }
-        *(gu64 *)((gcu8 *)v.spins + (xo + L.oc)) = Wc ^ (((uint64_t)flip_h << 32) | flip_l);
+        st64<COH>(v.spins, xo + L.oc, Wc ^ (((uint64_t)flip_h << 32) | flip_l));
         dsum += step;
         if (first) dfirst = step;
         first = false;
@@ -552,15 +589,16 @@ struct BpStep {
     uint32_t S, A, yp, ym, xp;
 };
 
-__device__ __forceinline__ BpStep bp_load_step(const gcu8 *base, uint32_t own, uint32_t edge, uint32_t RWB,
+template <bool COH>
+__device__ __forceinline__ BpStep bp_load_step(const uint8_t *sp, uint32_t own, uint32_t edge, uint32_t RWB,
                                                uint32_t XB, bool has_xp)
 {
     BpStep n;
-    n.S = *(gcu32 *)(base + own);
-    n.A = *(gcu32 *)(base + edge);
-    n.yp = *(gcu32 *)(base + (own + RWB));
-    n.ym = *(gcu32 *)(base + (own - RWB));
-    n.xp = has_xp ? *(gcu32 *)(base + (own + XB)) : 0u;
+    n.S = ld32<COH>(sp, own);
+    n.A = ld32<COH>(sp, edge);
+    n.yp = ld32<COH>(sp, own + RWB);
+    n.ym = ld32<COH>(sp, own - RWB);
+    n.xp = has_xp ? ld32<COH>(sp, own + XB) : 0u;
     return n;
 }
 
@@ -700,7 +738,7 @@ __device__ __forceinline__ uint32_t bp_flips(uint32_t S, uint32_t b2, uint32_t b
     return F;
 }
 
-template <bool NEVER>
+template <bool NEVER, bool COH>
 __device__ __forceinline__ void bp_march(const RepView &v, const Entry &en, int k_lo, int k_hi, int parity,
                                          const Tables *tb, Acc &a)
 {
@@ -711,8 +749,6 @@ __device__ __forceinline__ void bp_march(const RepView &v, const Entry &en, int 
     const uint32_t SB = 4u * (uint32_t)Wq;    // bytes of one sublattice row
     const uint32_t RWB = 2u * SB;             // bytes of one row
     const uint32_t XB = (uint32_t)Ly * RWB;   // bytes of one x plane
-    const gcu8 *base = (const gcu8 *)v.spins;
-    gu32 *wout = (gu32 *)v.spins;
     const int nb_here = min(32, nbits - 32 * w);
     const uint32_t vmask = nb_here >= 32 ? 0xFFFFFFFFu : ((1u << nb_here) - 1u);
     // z edges: an even-z word (q = 0) needs bit 31 of odd word w-1 (the last
@@ -734,9 +770,9 @@ __device__ __forceinline__ void bp_march(const RepView &v, const Entry &en, int 
 
     auto own_of = [&](uint32_t r, int qq) { return r + (qq ? SB : 0u); };
     auto edge_of = [&](uint32_t r, int qq) { return r - 4u * (uint32_t)w + (qq ? e1 : SB + e0); };
-    uint32_t O = *(gcu32 *)(base + own_of(rw, q ^ 1));
-    uint32_t xm = (x0 > 0) ? *(gcu32 *)(base + own_of(rw, q) - XB) : 0u;
-    BpStep cur = bp_load_step(base, own_of(rw, q), edge_of(rw, q), RWB, XB, x0 < Lx - 1);
+    uint32_t O = ld32<COH>(v.spins, own_of(rw, q ^ 1));
+    uint32_t xm = (x0 > 0) ? ld32<COH>(v.spins, own_of(rw, q) - XB) : 0u;
+    BpStep cur = bp_load_step<COH>(v.spins, own_of(rw, q), edge_of(rw, q), RWB, XB, x0 < Lx - 1);
     // per-thread sums over the flipped sites of the march: NF = flips, NFU =
     // flips of up spins, A0..A2 = bit planes of a' = c (up) or 7 - c (down),
     // c = up neighbours; KDM = sum of (6 - k) dm over the surface planes
@@ -745,7 +781,7 @@ __device__ __forceinline__ void bp_march(const RepView &v, const Entry &en, int 
         const uint32_t own = own_of(rw, q);
         BpStep nxt;
         const bool more = x + 1 < x1;
-        if (more) nxt = bp_load_step(base, own_of(rw + XB, q ^ 1), edge_of(rw + XB, q ^ 1), RWB, XB, x + 2 < Lx);
+        if (more) nxt = bp_load_step<COH>(v.spins, own_of(rw + XB, q ^ 1), edge_of(rw + XB, q ^ 1), RWB, XB, x + 2 < Lx);
         const uint32_t S = cur.S;
         const uint32_t zm = q ? O : ((O << 1) | ((cur.A >> csh0) & 1u));
         const uint32_t zp = q ? ((O >> 1) | ((cur.A & 1u) << zsh1)) : O;
@@ -762,7 +798,7 @@ __device__ __forceinline__ void bp_march(const RepView &v, const Entry &en, int 
         if (!NEVER && bulk) F = bp_flips_pairs(S, b2, b1, b0, gq, v, tb);
         else F = bp_flips<NEVER>(S, b2, b1, b0, gq, v, tb, (x == 0 ? 1 : 0) + (x == Lx - 1 ? 2 : 0));
         F &= vmask;
-        wout[own >> 2] = S ^ F;
+        st32<COH>(v.spins, own, S ^ F);
         const uint32_t FU = F & S;
         NF += __popc(F);
         NFU += __popc(FU);
@@ -818,7 +854,9 @@ __device__ __forceinline__ void bp_march(const RepView &v, const Entry &en, int 
 // number of columns) in the fields (rep, x0, y0, j0, nsteps).
 // ---------------------------------------------------------------------------
 // One wave folds the spread partial sums of sweep t of one replica into its
-// running observables and record (slots read and cleared atomically).
+// running observables and record (slots read and cleared atomically; COH:
+// the running sums are read and written device-coherently).
+template <bool COH>
 __device__ __forceinline__ void fold_sweep(const RepDesc &d, RepState &sr, uint32_t t, int lane)
 {
     long long *slot = d.acc + ((size_t)(t & 1) * kAccSlots + lane) * 4;
@@ -831,12 +869,19 @@ __device__ __forceinline__ void fold_sweep(const RepDesc &d, RepState &sr, uint3
         for (int off = 32; off > 0; off >>= 1) v[k] += __shfl_xor(v[k], off, 64);
     }
     if (lane == 0) {
+        long long c[4];
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            c[k] = COH ? __hip_atomic_load(&sr.cur[k], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) : sr.cur[k];
+            c[k] += v[k];
+            if (COH) __hip_atomic_store(&sr.cur[k], c[k], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            else sr.cur[k] = c[k];
+        }
         islf_obs o;
-        o.B = sr.cur[0] + v[0];
-        o.M = sr.cur[1] + v[1];
-        o.M1 = sr.cur[2] + v[2];
-        o.Mn = sr.cur[3] + v[3];
-        sr.cur[0] = o.B; sr.cur[1] = o.M; sr.cur[2] = o.M1; sr.cur[3] = o.Mn;
+        o.B = c[0];
+        o.M = c[1];
+        o.M1 = c[2];
+        o.Mn = c[3];
         d.rec[t % d.cap] = o;
     }
 }
@@ -844,6 +889,7 @@ __device__ __forceinline__ void fold_sweep(const RepDesc &d, RepState &sr, uint3
 // Wave w of the grid (blockIdx * 4 + wave) folds sweep st.t + s of the listed
 // replicas w, w + 4*grid, ...; with `advance` it then moves their sweep
 // counters on by that much.  Waves only: no workgroup barrier.
+template <bool COH>
 __device__ __forceinline__ void fold_waves(const RepDesc *__restrict__ descs, RepState *__restrict__ st,
                                            const int *__restrict__ reps, int n_reps, uint32_t s, uint32_t advance)
 {
@@ -851,7 +897,7 @@ __device__ __forceinline__ void fold_waves(const RepDesc *__restrict__ descs, Re
     const int per_block = kBlock / 64;
     for (int i = blockIdx.x * per_block + (threadIdx.x >> 6); i < n_reps; i += gridDim.x * per_block) {
         const int r = reps[i];
-        fold_sweep(descs[r], st[r], st[r].t + s, lane);
+        fold_sweep<COH>(descs[r], st[r], st[r].t + s, lane);
         if (advance && lane == 0) st[r].t += advance;
     }
 }
@@ -860,7 +906,7 @@ __device__ __forceinline__ void fold_waves(const RepDesc *__restrict__ descs, Re
 // one row when Ly = 2; 2/3: row 0) and the parity; the x pairs and the
 // columns come from the entry.  Sites of one phase are never neighbours, so
 // the tasks of a stage are independent.
-template <int FMT>
+template <int FMT, bool COH>
 __device__ __forceinline__ void slab_stage(const RepView &v, const Entry &en, int phase, const Tables *tb, Acc &a)
 {
     const int Lx = v.Lx, Ly = v.Ly;
@@ -876,14 +922,14 @@ __device__ __forceinline__ void slab_stage(const RepView &v, const Entry &en, in
         const int x = (xi & 1) ? Lx - 1 - p : p;
         if ((xi & 1) && x == p) continue;   // the middle plane of an odd Lx pairs with itself
         const int y = phase >= 2 ? 0 : (ri == 0 ? 1 : Ly - 1);
-        if (FMT == ISLF_SPIN_INT8) i8_update_chunk(v, x, y, j0 + jj, phase & 1, tb->thr, a);
-        else bp_update_word(v, x, y, j0 + jj, phase & 1, tb->thr, a);
+        if (FMT == ISLF_SPIN_INT8) i8_update_chunk<COH>(v, x, y, j0 + jj, phase & 1, tb->thr, a);
+        else bp_update_word<COH>(v, x, y, j0 + jj, phase & 1, tb->thr, a);
     }
 }
 
 // One slab entry of launch KIND for sweep st.t + s; ends with a workgroup
 // barrier (in the last flush).
-template <int FMT, int KIND>
+template <int FMT, int KIND, bool COH>
 __device__ __forceinline__ void slab_entry(const RepDesc *__restrict__ descs, const RepState *__restrict__ st,
                                            const Entry &en, uint32_t s, uint32_t flags, Tables *tb)
 {
@@ -896,18 +942,18 @@ __device__ __forceinline__ void slab_entry(const RepDesc *__restrict__ descs, co
         if (flags & FLAG_PREV) {
             RepView vp = v;
             vp.t = v.t - 1;
-            slab_stage<FMT>(vp, en, 3, tb, a);
+            slab_stage<FMT, COH>(vp, en, 3, tb, a);
             flush_acc(a, v.acc, vp.t, slot);   // its barrier also orders the two stages
         }
-        slab_stage<FMT>(v, en, 0, tb, a);
+        slab_stage<FMT, COH>(v, en, 0, tb, a);
         flush_acc(a, v.acc, v.t, slot);
     } else if (KIND == KIND_B) {
-        slab_stage<FMT>(v, en, 1, tb, a);
+        slab_stage<FMT, COH>(v, en, 1, tb, a);
         flush_acc(a, v.acc, v.t, slot);
-        slab_stage<FMT>(v, en, 2, tb, a);
+        slab_stage<FMT, COH>(v, en, 2, tb, a);
         flush_acc(a, v.acc, v.t, slot);
     } else {
-        slab_stage<FMT>(v, en, 3, tb, a);
+        slab_stage<FMT, COH>(v, en, 3, tb, a);
         flush_acc(a, v.acc, v.t, slot);
     }
 }
@@ -915,7 +961,7 @@ __device__ __forceinline__ void slab_entry(const RepDesc *__restrict__ descs, co
 // One main tile piece (rows 2 .. Ly-2), x steps [k_lo, k_hi), of launch A
 // (phase 0) or B (phase 1), with the replica's view and tables in place;
 // adds its changes of the observables to a.
-template <int FMT, int KIND>
+template <int FMT, int KIND, bool COH>
 __device__ __forceinline__ void main_piece(const RepView &v, const Entry &en, int k_lo, int k_hi, const Tables *tb,
                                            Acc &a)
 {
@@ -923,15 +969,15 @@ __device__ __forceinline__ void main_piece(const RepView &v, const Entry &en, in
     if (FMT == ISLF_SPIN_INT8) {
         const bool ragged = (v.Lz & 7) != 0;
         if (v.never) {
-            if (ragged) i8_march<true, true>(v, en, k_lo, k_hi, parity, tb, a);
-            else i8_march<true, false>(v, en, k_lo, k_hi, parity, tb, a);
+            if (ragged) i8_march<true, true, COH>(v, en, k_lo, k_hi, parity, tb, a);
+            else i8_march<true, false, COH>(v, en, k_lo, k_hi, parity, tb, a);
         } else {
-            if (ragged) i8_march<false, true>(v, en, k_lo, k_hi, parity, tb, a);
-            else i8_march<false, false>(v, en, k_lo, k_hi, parity, tb, a);
+            if (ragged) i8_march<false, true, COH>(v, en, k_lo, k_hi, parity, tb, a);
+            else i8_march<false, false, COH>(v, en, k_lo, k_hi, parity, tb, a);
         }
     } else {
-        if (v.never) bp_march<true>(v, en, k_lo, k_hi, parity, tb, a);
-        else bp_march<false>(v, en, k_lo, k_hi, parity, tb, a);
+        if (v.never) bp_march<true, COH>(v, en, k_lo, k_hi, parity, tb, a);
+        else bp_march<false, COH>(v, en, k_lo, k_hi, parity, tb, a);
     }
 }
 
@@ -948,7 +994,7 @@ __device__ __forceinline__ int plan_block()
     return x * q + min(x, r) + (b >> 3);
 }
 
-template <int FMT, int KIND>
+template <int FMT, int KIND, bool COH>
 __device__ __forceinline__ void run_items(const RepDesc *__restrict__ descs, const RepState *__restrict__ st,
                                           const Entry *__restrict__ items, int i0, int i1, uint32_t s,
                                           uint32_t flags, Tables *tb)
@@ -960,7 +1006,7 @@ __device__ __forceinline__ void run_items(const RepDesc *__restrict__ descs, con
     for (; i < i1; ++i) {
         const Entry en = items[i];
         if (en.kind != ITEM_SLAB) break;
-        slab_entry<FMT, KIND>(descs, st, en, s, flags, tb);
+        slab_entry<FMT, KIND, COH>(descs, st, en, s, flags, tb);
     }
     if (KIND == KIND_F) return;
     const int slot = blockIdx.x & (kAccSlots - 1);
@@ -976,7 +1022,7 @@ __device__ __forceinline__ void run_items(const RepDesc *__restrict__ descs, con
             __syncthreads();
             cur = en.rep;
         }
-        main_piece<FMT, KIND>(v, en, 0, en.nsteps, tb, a);
+        main_piece<FMT, KIND, COH>(v, en, 0, en.nsteps, tb, a);
     }
     if (cur >= 0) flush_acc(a, v.acc, v.t, slot);
 }
@@ -991,9 +1037,9 @@ __global__ __launch_bounds__(kBlock) void k_sweep(const RepDesc *__restrict__ de
                                                   uint32_t flags)
 {
     __shared__ Tables tb;
-    if (KIND == KIND_B && (flags & FLAG_FOLD)) fold_waves(descs, st, reps, n_reps, s - 1, 0u);
+    if (KIND == KIND_B && (flags & FLAG_FOLD)) fold_waves<false>(descs, st, reps, n_reps, s - 1, 0u);
     const int b = plan_block();
-    run_items<FMT, KIND>(descs, st, items, first[b], first[b + 1], s, flags, &tb);
+    run_items<FMT, KIND, false>(descs, st, items, first[b], first[b + 1], s, flags, &tb);
 }
 
 // Closes a run of sweeps: folds sweep st.t + s and advances the counters.
@@ -1001,17 +1047,14 @@ __global__ __launch_bounds__(kBlock) void k_fold(const RepDesc *__restrict__ des
                                                  const int *__restrict__ reps, int n_reps, uint32_t s,
                                                  uint32_t advance)
 {
-    fold_waves(descs, st, reps, n_reps, s, advance);
+    fold_waves<false>(descs, st, reps, n_reps, s, advance);
 }
 
 // ---------------------------------------------------------------------------
 // Persistent form: the same schedule inside one cooperative launch, with a
 // bounded two-level grid barrier in place of each launch boundary.
 // ---------------------------------------------------------------------------
-// Polls a barrier word.  Relaxed: an acquire load invalidates the XCD's L2 on
-// every poll, which evicts the lattice data of the blocks still working;
-// grid_barrier orders the data with one fence after the wait instead (a
-// relaxed load that sees the releasing increment, then an acquire fence).
+// Polls a barrier word (a device-coherent load).
 __device__ __forceinline__ unsigned long long sync_load(unsigned long long *p)
 {
     return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
@@ -1032,8 +1075,20 @@ __device__ __forceinline__ bool sync_wait(GridSync *sync, unsigned long long *p,
 }
 
 // Barrier number k (= passed) of a launch: two-level arrival, see GridSync.
+// Everything the persistent kernel's blocks share across a barrier (lattice
+// words, running sums, accumulator slots, barrier words) is accessed
+// device-coherently: coherent loads and stores or device-scope atomics, none
+// of which leaves a line that another XCD could miss in its L2 or find stale
+// in its own.  The barrier therefore orders them by completion alone: every
+// wave waits until its memory operations are complete before the workgroup
+// meets, thread 0 arrives with a device-scope atomic once they all are, and
+// no wave issues a load of the next phase before thread 0 has seen the last
+// arrival.  The fences are workgroup-scope (they order the compiler and the
+// workgroup): device-scope fences would write back and invalidate the whole
+// L2 at each barrier.
 __device__ bool grid_barrier(GridSync *sync, unsigned long long nblocks, unsigned long long &passed)
 {
+    __builtin_amdgcn_s_waitcnt(0);   // all counters: this wave's loads and stores are complete
     __syncthreads();
     __shared__ int ok;
     if (threadIdx.x == 0) {
@@ -1042,8 +1097,7 @@ __device__ bool grid_barrier(GridSync *sync, unsigned long long nblocks, unsigne
         const unsigned long long g = blockIdx.x / kBarrierGroup;
         const unsigned long long gsize = min((unsigned long long)kBarrierGroup, nblocks - g * kBarrierGroup);
         bool good = true;
-        // release: this block's stores are written back before it arrives
-        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
         const unsigned long long old = atomicAdd(&sync->arrive[g].v, 1ull);
         if (old + 1 == k1 * gsize) {
             atomicAdd(&sync->top.v, 1ull);
@@ -1052,8 +1106,7 @@ __device__ bool grid_barrier(GridSync *sync, unsigned long long nblocks, unsigne
         } else {
             good = sync_wait(sync, &sync->release[g].v, k1);
         }
-        // acquire: stale cached lines are dropped before the next phase reads
-        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
         ok = good ? 1 : 0;
     }
     passed += 1;
@@ -1075,15 +1128,15 @@ __global__ __launch_bounds__(kBlock) void k_persistent(const RepDesc *__restrict
     const int i0 = first[b], i1 = first[b + 1];
     unsigned long long passed = 0;
     for (uint32_t s = 0; s < n_sweeps; ++s) {
-        run_items<FMT, KIND_A>(descs, st, items, i0, i1, s, s ? FLAG_PREV : 0u, &tb);
+        run_items<FMT, KIND_A, true>(descs, st, items, i0, i1, s, s ? FLAG_PREV : 0u, &tb);
         if (!grid_barrier(sync, G, passed)) return;
-        if (s > 0) fold_waves(descs, st, reps, n_reps, s - 1, 0u);
-        run_items<FMT, KIND_B>(descs, st, items, i0, i1, s, 0u, &tb);
+        if (s > 0) fold_waves<true>(descs, st, reps, n_reps, s - 1, 0u);
+        run_items<FMT, KIND_B, true>(descs, st, items, i0, i1, s, 0u, &tb);
         if (!grid_barrier(sync, G, passed)) return;
     }
-    run_items<FMT, KIND_F>(descs, st, items, i0, i1, n_sweeps - 1, 0u, &tb);
+    run_items<FMT, KIND_F, true>(descs, st, items, i0, i1, n_sweeps - 1, 0u, &tb);
     if (!grid_barrier(sync, G, passed)) return;
-    fold_waves(descs, st, reps, n_reps, n_sweeps - 1, n_sweeps);
+    fold_waves<true>(descs, st, reps, n_reps, n_sweeps - 1, n_sweeps);
 }
 
 // ---------------------------------------------------------------------------

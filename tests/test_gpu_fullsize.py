@@ -50,6 +50,7 @@ def oracle_T3():
                                                  (islf.BITPACK, islf.EXEC_BATCHED, False),
                                                  (islf.BITPACK, islf.EXEC_BATCHED, True),
                                                  (islf.INT8, islf.EXEC_PERSISTENT, False),
+                                                 (islf.BITPACK, islf.EXEC_PERSISTENT, False),
                                                  (islf.INT8, islf.EXEC_PLAIN, False)])
 def test_paper_scale_two_sweeps_bit_exact(oracle_T3, fmt, exec_mode, graph):
     p, th, out = oracle_T3
@@ -75,22 +76,28 @@ def test_paper_scale_two_sweeps_bit_exact(oracle_T3, fmt, exec_mode, graph):
 
 
 def test_paper_scale_long_run_properties():
-    """200 sweeps: reductions == recompute, int8 == bit-packed, |M| <= N, B in range."""
+    """200 sweeps: reductions == recompute, int8 == bit-packed == the persistent
+    form (whose blocks exchange every plane through device-coherent accesses
+    across its grid barriers), |M| <= N, B in range."""
     N = SHAPE[0] * SHAPE[1] * SHAPE[2]
     res = {}
-    for fmt in (islf.INT8, islf.BITPACK):
+    runs = ((islf.INT8, islf.EXEC_BATCHED), (islf.BITPACK, islf.EXEC_BATCHED), (islf.BITPACK, islf.EXEC_PERSISTENT),
+            (islf.INT8, islf.EXEC_PERSISTENT))
+    for fmt, exec_mode in runs:
         reps = [islf.Replica(**params(T, i)) for i, T in enumerate((2.0, 3.0, 4.0))]
-        with islf.Context(reps, spin_format=fmt, obs_capacity=256, exec_mode=islf.EXEC_BATCHED) as ctx:
+        with islf.Context(reps, spin_format=fmt, obs_capacity=256, exec_mode=exec_mode) as ctx:
             ctx.capture(50)
             ctx.replay(4)
             recs = [ctx.measure(i, 0, 200) for i in range(3)]
             rcs = [ctx.recompute(i) for i in range(3)]
             spins = [ctx.get_spins(i) for i in range(3)]
-        res[fmt] = (recs, rcs, spins)
+        res[fmt, exec_mode] = (recs, rcs, spins)
         for r, rc in zip(recs, rcs):
             assert np.array_equal(r[-1], rc)
             assert (np.abs(r[:, 1]) <= N).all()
             assert (np.abs(r[:, 0]) <= 3 * N).all()
-    for i in range(3):
-        assert np.array_equal(res[islf.INT8][0][i], res[islf.BITPACK][0][i])
-        assert np.array_equal(res[islf.INT8][2][i], res[islf.BITPACK][2][i])
+    ref = res[runs[0]]
+    for run in runs[1:]:
+        for i in range(3):
+            assert np.array_equal(ref[0][i], res[run][0][i]), (run, i)
+            assert np.array_equal(ref[2][i], res[run][2][i]), (run, i)
