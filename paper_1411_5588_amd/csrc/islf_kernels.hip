@@ -181,9 +181,9 @@ typedef __attribute__((address_space(1))) uint8_t gu8;
 
 // Lattice accesses.  COH (the persistent kernel) makes them relaxed
 // device-scope atomics, which the compiler marks device-coherent: stores
-// write through the XCD's L2 and loads do not use a stale copy in it, so the
-// L2 holds no dirty lattice lines when the grid barrier writes it back and
-// loses no data the next phase needs when the barrier invalidates it.
+// write through the XCD's L2 and loads do not use a stale copy in it, so a
+// block on any XCD sees another's stores once they are complete, and the
+// grid barrier needs no L2 write-back or invalidate (see grid_barrier).
 template <bool COH>
 __device__ __forceinline__ uint64_t ld64(const uint8_t *base, uint32_t off)
 {
