@@ -443,8 +443,9 @@ static double tail_taper(int fmt)
 constexpr double kPlainTaper = 0.2;
 // the persistent launch has no second round of workgroups to fill a CU
 // whose resident workgroups finish at different times (issue goes oldest
-// first), so its shares are tapered harder: 0.3-0.4 measured best, 5% over 0.2
-constexpr double kPersistentTaper = 0.4;
+// first); with its barriers free of cache maintenance a light taper is best
+// in both formats (0.1 measured: 3-7% over 0.4, the best of 0 .. 0.5)
+constexpr double kPersistentTaper = 0.1;
 // three concurrent groups: measured as fast as two and faster than four on
 // every batch tried (3 x 160x480x600, 64 x 40x120x120, 96 uneven replicas);
 // four group streams can share one of the process's four hardware queues
