@@ -330,7 +330,8 @@ def main():
 
     forms = {}
     if not args.no_extras:
-        for form, fmt in (("plain", "bitpack"), ("batched", "int8"), ("plain", "int8"), ("persistent", "bitpack")):
+        for form, fmt in (("plain", "bitpack"), ("batched", "int8"), ("plain", "int8"), ("persistent", "bitpack"),
+                          ("persistent", "int8")):
             if (form, fmt) == (args.form, args.fmt):
                 continue
             r = run_form(islf, torch, form, fmt, min(args.steps, 100), min(args.chunk, 50), min(args.chunk, 50))
