@@ -167,10 +167,11 @@ islf_status islf_measure(islf_ctx *ctx, int32_t rep, uint64_t first, uint32_t co
  * the device (a check of the fused per-sweep reductions); synchronises. */
 islf_status islf_recompute(islf_ctx *ctx, int32_t rep, islf_obs *out);
 
-/* Energies E = ((-J B - H M) - h1 M1) - hn Mn (Eq. 1, IEEE double, left to
- * right) of records first .. first+count-1, computed on the device and copied
- * to host out[count]; synchronises.  Errors as islf_measure. */
-islf_status islf_energy(islf_ctx *ctx, int32_t rep, uint64_t first, uint32_t count, double *out);
+/* Energies of one replica's records on the device: E = ((-J B - H M) - h1 M1)
+ * - hn Mn (Eq. 1, IEEE double, left to right) of records first ..
+ * first+count-1, computed by a kernel and copied to host out[count];
+ * synchronises.  Errors as islf_measure. */
+islf_status islf_record_energy(islf_ctx *ctx, int32_t rep, uint64_t first, uint32_t count, double *out);
 
 /* Per-replica means over records first .. first+count-1 of every live
  * replica, computed on the device as (double)(exact int64 sum) / (double)count:
@@ -184,18 +185,40 @@ islf_status islf_means(islf_ctx *ctx, uint64_t first, uint32_t count, double *ou
 islf_status islf_replica_means(islf_ctx *ctx, int32_t rep, uint64_t first, uint32_t count, double *out);
 
 /* ---------------------------------------------------------------------- */
-/* Thermodynamic integration over the surface field (Eq. 9, Eq. 22)        */
+/* Host FP64 post-processing (Sec. II.A Eq. 1, Eq. 9; Sec. II.C Eq. 22)    */
 /* ---------------------------------------------------------------------- */
 
-/* Cumulative trapezoid on the device in IEEE double, left to right:
- *   g_r = norm * (c1 * m1[r] + cn * mn[r]),  out[0] = 0,
- *   out[r] = out[r-1] + (0.5 * (h[r] - h[r-1])) * (g_{r-1} + g_r).
+/* Energies of n observable records of one replica (Sec. II.A Eq. 1) on the
+ * host in IEEE double, left to right, no fused multiply-add:
+ *   E_out[k] = ((-J B_k - H M_k) - h1 M1_k) - hn Mn_k
+ * with J, H, h1, hn taken from *desc (its other fields are not used).
+ * desc, obs[n] and E_out[n] are host memory owned by the caller; no device
+ * is touched and nothing is allocated.  n = 0 is a no-op.
+ * Errors: EINVAL (NULL desc, or NULL obs / E_out with n > 0, or a
+ * non-finite J, H, h1, hn). */
+islf_status islf_energy(const islf_replica_desc *desc, const islf_obs *obs, size_t n, double *E_out);
+
+/* Thermodynamic integration over the surface field (Eq. 9; Eq. 22 along the
+ * field path of the inclined-interface film): a cumulative trapezoid on the
+ * host in IEEE double, left to right, no fused multiply-add:
+ *   g_r = norm * (c1 * mean_M1[r] + cn * mean_Mn[r]),  cumulative_out[0] = 0,
+ *   cumulative_out[r] = cumulative_out[r-1] + (0.5 * (h[r] - h[r-1])) * (g_{r-1} + g_r).
  * (c1, cn) = (-1, -1) is the literal integrand of Eq. 9; (-1, +1) integrates
- * the field-conjugate -<m1 - mn> along hn = -h1.  h, m1, mn, out are DEVICE
- * pointers to n doubles (n >= 1); runs on hip_stream and returns without
- * waiting.  Errors: EINVAL (n < 1, NULL). */
-islf_status islf_integrate(const double *h, const double *m1, const double *mn, int32_t n,
-                           double c1, double cn, double norm, double *out, void *hip_stream);
+ * the field-conjugate -<m1 - mn> along hn = -h1 (the Eq. 7 derivative).  With
+ * the means of the energy in place of mean_M1 / mean_Mn and (c1, cn) =
+ * (1, -1) the same rule integrates U_a - U_b over beta (Eq. 19).  h, mean_M1,
+ * mean_Mn and cumulative_out are host arrays of n doubles owned by the
+ * caller (n >= 1); no device is touched and nothing is allocated.
+ * Errors: EINVAL (n < 1, NULL). */
+islf_status islf_integrate(const double *h, const double *mean_M1, const double *mean_Mn, int32_t n, double c1,
+                           double cn, double norm, double *cumulative_out);
+
+/* The same trapezoid run by a kernel: h, m1, mn, out are DEVICE pointers to
+ * n doubles (n >= 1), enqueued on hip_stream without waiting, results
+ * bit-identical to islf_integrate.  For a pipeline whose means already sit in
+ * device memory.  Errors: EINVAL (n < 1, NULL), EDEVICE. */
+islf_status islf_integrate_device(const double *h, const double *m1, const double *mn, int32_t n, double c1,
+                                  double cn, double norm, double *out, void *hip_stream);
 
 /* ---------------------------------------------------------------------- */
 /* Batching and serving                                                    */

@@ -2,4 +2,4 @@
 of arXiv:1411.5588 (HIP kernels behind the C ABI in include/islf.h)."""
 from .islf import (APBC, BITPACK, EXEC_BATCHED, EXEC_PERSISTENT, EXEC_PLAIN, GAPBC, INIT_DOWN,  # noqa: F401
                    INIT_HOST, INIT_RANDOM, INIT_UP, INT8, PBC, Context, IslfError, Replica,
-                   footprint_bytes, integrate, num_tiles)
+                   energy, footprint_bytes, integrate, integrate_device, num_tiles)

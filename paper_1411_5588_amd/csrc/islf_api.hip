@@ -1180,7 +1180,8 @@ extern "C" islf_status islf_recompute(islf_ctx *ctx, int32_t rep, islf_obs *out)
     return ISLF_OK;
 }
 
-extern "C" islf_status islf_energy(islf_ctx *ctx, int32_t rep, uint64_t first, uint32_t count, double *out)
+extern "C" islf_status islf_record_energy(islf_ctx *ctx, int32_t rep, uint64_t first, uint32_t count,
+                                          double *out)
 {
     islf_status st = check_rep(ctx, rep);
     if (st != ISLF_OK) return st;
@@ -1229,8 +1230,47 @@ extern "C" islf_status islf_means(islf_ctx *ctx, uint64_t first, uint32_t count,
     return ISLF_OK;
 }
 
-extern "C" islf_status islf_integrate(const double *h, const double *m1, const double *mn, int32_t n, double c1,
-                                      double cn, double norm, double *out, void *hip_stream)
+// Host FP64 energies of records (Sec. II.A Eq. 1), in the order the header
+// states; plain C arithmetic (the library is built without FMA contraction).
+extern "C" islf_status islf_energy(const islf_replica_desc *desc, const islf_obs *obs, size_t n, double *E_out)
+{
+    if (!desc) return fail(ISLF_EINVAL, "NULL replica descriptor");
+    if (n > 0 && (!obs || !E_out)) return fail(ISLF_EINVAL, "NULL records or output");
+    const double J = desc->J, H = desc->H, h1 = desc->h1, hn = desc->hn;
+    if (!isfinite(J) || !isfinite(H) || !isfinite(h1) || !isfinite(hn))
+        return fail(ISLF_EINVAL, "J, H, h1, hn must be finite");
+    for (size_t k = 0; k < n; ++k) {
+        double e = -J * (double)obs[k].B;
+        e = e - H * (double)obs[k].M;
+        e = e - h1 * (double)obs[k].M1;
+        e = e - hn * (double)obs[k].Mn;
+        E_out[k] = e;
+    }
+    return ISLF_OK;
+}
+
+// Host FP64 cumulative trapezoid (Eq. 9 / Eq. 22 over the field, Eq. 19 over
+// beta), left to right.
+extern "C" islf_status islf_integrate(const double *h, const double *mean_M1, const double *mean_Mn, int32_t n,
+                                      double c1, double cn, double norm, double *cumulative_out)
+{
+    if (!h || !mean_M1 || !mean_Mn || !cumulative_out) return fail(ISLF_EINVAL, "NULL argument");
+    if (n < 1) return fail(ISLF_EINVAL, "need n >= 1 points");
+    double g_prev = norm * (c1 * mean_M1[0] + cn * mean_Mn[0]);
+    double acc = 0.0;
+    cumulative_out[0] = 0.0;
+    for (int32_t r = 1; r < n; ++r) {
+        const double g = norm * (c1 * mean_M1[r] + cn * mean_Mn[r]);
+        const double step = 0.5 * (h[r] - h[r - 1]);
+        acc = acc + step * (g_prev + g);
+        cumulative_out[r] = acc;
+        g_prev = g;
+    }
+    return ISLF_OK;
+}
+
+extern "C" islf_status islf_integrate_device(const double *h, const double *m1, const double *mn, int32_t n,
+                                             double c1, double cn, double norm, double *out, void *hip_stream)
 {
     if (!h || !m1 || !mn || !out) return fail(ISLF_EINVAL, "NULL argument");
     if (n < 1) return fail(ISLF_EINVAL, "need n >= 1 points");

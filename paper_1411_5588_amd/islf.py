@@ -98,9 +98,11 @@ def lib():
             "islf_sweep_count": [vp, i32, P(u64)],
             "islf_measure": [vp, i32, u64, u32, vp],
             "islf_recompute": [vp, i32, P(Obs)],
-            "islf_energy": [vp, i32, u64, u32, vp],
+            "islf_record_energy": [vp, i32, u64, u32, vp],
+            "islf_energy": [P(ReplicaDesc), vp, sz, vp],
             "islf_means": [vp, u64, u32, vp],
-            "islf_integrate": [vp, vp, vp, i32, dbl, dbl, dbl, vp, vp],
+            "islf_integrate": [vp, vp, vp, i32, dbl, dbl, dbl, vp],
+            "islf_integrate_device": [vp, vp, vp, i32, dbl, dbl, dbl, vp, vp],
             "islf_footprint_bytes": [P(ReplicaDesc), i32, u32, P(u64)],
             "islf_plan_preview": [vp, i32, i32, i32, i32, vp, vp, i32, P(i32), vp, i32, P(i32)],
             "islf_batch_add": [vp, P(ReplicaDesc), P(i32)],
@@ -259,7 +261,7 @@ class Context:
         if count is None:
             count = self.sweep_count(rep) - first
         out = np.zeros(count, dtype=np.float64)
-        _check(lib().islf_energy(self._h, rep, first, count, out.ctypes.data_as(C.c_void_p)))
+        _check(lib().islf_record_energy(self._h, rep, first, count, out.ctypes.data_as(C.c_void_p)))
         return out
 
     def means(self, first, count) -> np.ndarray:
@@ -388,8 +390,34 @@ def plan_preview(replicas, spin_format=INT8, tile=-1, grid=2048):
     return {"shapes": shapes, "items": items[:ni.value], "first": first[:nf.value]}
 
 
-def integrate(h, m1, mn, c1=-1.0, cn=1.0, norm=1.0, stream=None):
-    """Cumulative trapezoid of g = norm (c1 m1 + cn mn) over h on the GPU (Eq. 9).
+def energy(replica: Replica, records) -> np.ndarray:
+    """Eq. 1 energies of (n, 4) int64 records (B, M, M1, Mn) with the
+    replica's J, H, h1, hn: host FP64, no GPU (islf_energy)."""
+    rec = np.ascontiguousarray(np.asarray(records, dtype=np.int64).reshape(-1, 4))
+    out = np.zeros(rec.shape[0], dtype=np.float64)
+    d = replica.to_c()
+    _check(lib().islf_energy(C.byref(d), rec.ctypes.data_as(C.c_void_p), rec.shape[0],
+                             out.ctypes.data_as(C.c_void_p)))
+    return out
+
+
+def integrate(h, mean_m1, mean_mn, c1=-1.0, cn=1.0, norm=1.0) -> np.ndarray:
+    """Cumulative trapezoid of g = norm (c1 m1 + cn mn) over h (Eq. 9 / Eq. 22):
+    host FP64 arrays in and out, no GPU (islf_integrate)."""
+    h = np.ascontiguousarray(h, dtype=np.float64)
+    m1 = np.ascontiguousarray(mean_m1, dtype=np.float64)
+    mn = np.ascontiguousarray(mean_mn, dtype=np.float64)
+    if not (h.shape == m1.shape == mn.shape) or h.ndim != 1:
+        raise ValueError("h, mean_m1, mean_mn must be 1-D arrays of one length")
+    out = np.zeros(h.size, dtype=np.float64)
+    _check(lib().islf_integrate(h.ctypes.data_as(C.c_void_p), m1.ctypes.data_as(C.c_void_p),
+                                mn.ctypes.data_as(C.c_void_p), h.size, c1, cn, norm,
+                                out.ctypes.data_as(C.c_void_p)))
+    return out
+
+
+def integrate_device(h, m1, mn, c1=-1.0, cn=1.0, norm=1.0, stream=None):
+    """The same trapezoid by a kernel on the GPU (islf_integrate_device).
 
     Inputs are torch float64 CUDA tensors (or array-likes, copied to the GPU).
     Returns a float64 CUDA tensor.
@@ -401,6 +429,7 @@ def integrate(h, m1, mn, c1=-1.0, cn=1.0, norm=1.0, stream=None):
     mn = torch.as_tensor(mn, dtype=torch.float64, device=dev).contiguous()
     out = torch.empty_like(h)
     s = stream if stream is not None else torch.cuda.current_stream()
-    _check(lib().islf_integrate(C.c_void_p(h.data_ptr()), C.c_void_p(m1.data_ptr()), C.c_void_p(mn.data_ptr()),
-                                h.numel(), c1, cn, norm, C.c_void_p(out.data_ptr()), C.c_void_p(s.cuda_stream)))
+    _check(lib().islf_integrate_device(C.c_void_p(h.data_ptr()), C.c_void_p(m1.data_ptr()),
+                                       C.c_void_p(mn.data_ptr()), h.numel(), c1, cn, norm,
+                                       C.c_void_p(out.data_ptr()), C.c_void_p(s.cuda_stream)))
     return out

@@ -38,16 +38,17 @@ def test_beta_ladder_matches_oracle(fmt):
     def run(p):
         L = oracle_lattice(p)
         rec = L.run(n)
-        B, M, M1, Mn = [O.mean(rec, c, t0, n - t0) for c in range(4)]
-        # mean energy: Eq. 1 applied to the mean records, left to right
-        return ((-p["J"] * B - p["H"] * M) - p["h1"] * M1) - p["hn"] * Mn
+        means = np.array([O.mean(rec, c, t0, n - t0) for c in range(4)])
+        # mean energy: the oracle's Eq. 1 applied to the mean records
+        return O.energy(p["J"], p["H"], p["h1"], p["hn"], means)
 
     om = np.array(parallel_map(run, params))
     assert np.array_equal(gm[:, 0], om)
     k = len(betas)
     ua, up = gm[:k, 0], gm[k:, 0]
     # device trapezoid of (U_APBC - U_PBC) over beta vs the oracle's
-    dev = islf.integrate(betas, ua, up, c1=1.0, cn=-1.0, norm=1.0).cpu().numpy()
+    dev = islf.integrate_device(betas, ua, up, c1=1.0, cn=-1.0, norm=1.0).cpu().numpy()
+    assert np.array_equal(dev, islf.integrate(betas, ua, up, c1=1.0, cn=-1.0, norm=1.0))
     ref = O.integrate(betas, om[:k], om[k:], c1=1.0, cn=-1.0, norm=1.0)
     assert np.allclose(dev, ref, rtol=1e-12, atol=1e-12)
     dF = A.delta_free_energy(betas, ua, up)

@@ -63,7 +63,7 @@ def test_ti_batch_persistent_graph(fmt):
         spins = {i: ctx.get_spins(i) for i in (0, 31, 63)}
         means = ctx.means(0, n)
         h = np.array([p["h1"] for p in ps])
-        cum = islf.integrate(h, means[:, 3], means[:, 4], -1.0, 1.0, 1.0 / (120 * 120)).cpu().numpy()
+        cum = islf.integrate_device(h, means[:, 3], means[:, 4], -1.0, 1.0, 1.0 / (120 * 120)).cpu().numpy()
     for i in range(64):
         assert np.array_equal(recs[i][-1], rc[i]), i
     check_sample(ps, spins, recs, [0, 31, 63], n)

@@ -33,6 +33,8 @@ def test_energy_records_match_oracle():
     assert np.array_equal(rec, o_rec)
     ref = np.array([O.energy(p["J"], p["H"], p["h1"], p["hn"], r) for r in o_rec])
     assert np.array_equal(e, ref)
+    # the host-array boundary call (islf_energy) on the device records
+    assert np.array_equal(islf.energy(islf.Replica(**p), rec), ref)
 
 
 def test_means_and_ti_pipeline_match_oracle():
@@ -48,14 +50,17 @@ def test_means_and_ti_pipeline_match_oracle():
         m1 = torch.tensor(means[:, 3], dtype=torch.float64, device="cuda")
         mn = torch.tensor(means[:, 4], dtype=torch.float64, device="cuda")
         norm = 1.0 / (12 * 12)
-        cum = islf.integrate(hs, m1, mn, -1.0, 1.0, norm).cpu().numpy()
-        lit = islf.integrate(hs, m1, mn, -1.0, -1.0, norm).cpu().numpy()
+        cum = islf.integrate_device(hs, m1, mn, -1.0, 1.0, norm).cpu().numpy()
+        lit = islf.integrate_device(hs, m1, mn, -1.0, -1.0, norm).cpu().numpy()
+    # the host-array boundary call on the same means
+    host = islf.integrate(hs, means[:, 3], means[:, 4], -1.0, 1.0, norm)
+    assert np.array_equal(host, cum)
     outs = parallel_map(lambda p: oracle_trajectory(p, n)[1], ps)
     for r, o_rec in enumerate(outs):
         om = [O.mean(o_rec, k, first=t0) for k in range(4)]
         assert np.array_equal(means[r, 1:], om), r
-        e_ref = ((-ps[r]["J"] * om[0] - ps[r]["H"] * om[1]) - ps[r]["h1"] * om[2]) - ps[r]["hn"] * om[3]
-        assert means[r, 0] == e_ref
+        # mean energy: the oracle's Eq. 1 evaluated at the mean observables
+        assert means[r, 0] == O.energy(ps[r]["J"], ps[r]["H"], ps[r]["h1"], ps[r]["hn"], np.array(om))
     o_m1 = np.array([O.mean(o, 2, first=t0) for o in outs])
     o_mn = np.array([O.mean(o, 3, first=t0) for o in outs])
     ref = O.integrate(hs, o_m1, o_mn, -1.0, 1.0, norm)
@@ -64,12 +69,13 @@ def test_means_and_ti_pipeline_match_oracle():
 
 
 def test_integrate_edge_cases():
-    one = islf.integrate([0.5], [1.0], [2.0]).cpu().numpy()
+    one = islf.integrate_device([0.5], [1.0], [2.0]).cpu().numpy()
     assert one.tolist() == [0.0]
     rng = np.random.default_rng(1)
     h = np.sort(rng.uniform(-1, 1, 513))
     m1, mn = rng.normal(size=513), rng.normal(size=513)
-    got = islf.integrate(h, m1, mn, 0.3, -1.7, 0.01).cpu().numpy()
+    got = islf.integrate_device(h, m1, mn, 0.3, -1.7, 0.01).cpu().numpy()
     assert np.array_equal(got, O.integrate(h, m1, mn, 0.3, -1.7, 0.01))
+    assert np.array_equal(got, islf.integrate(h, m1, mn, 0.3, -1.7, 0.01))
     with pytest.raises(islf.IslfError):
-        islf.integrate([], [], [])
+        islf.integrate_device([], [], [])
