@@ -9,20 +9,23 @@ checkerboard phases with the fused per-sweep observable reductions and the
 per-sweep record.  Inputs are synthetic (seeded) and resident in HBM before
 timing starts; nothing is copied to the host inside the timed region.
 
-Prints one JSON line.  Besides the headline (bit-packed spins, batched form)
-it reports the int8 format and the plain one-lattice-per-launch and
-persistent forms on the same workload, the roofline of the dominant kernel
+Prints one JSON line.  Besides the headline (batched form) it reports the
+other spin format, the plain one-lattice-per-launch and persistent forms on
+the same workload, a batch larger than the last-level cache, the batched
+thermodynamic-integration batch (64 x 40x120x120 along the surface field),
+the uneven autotuned batch (96 replicas of nine shapes) and the serving loop
+(Poisson arrivals, p50/p99 latency); the HBM roofline of the dominant kernel
 (the sweep kernel) and the CPU oracle timed on a bounded sample of the same
 workload.
 
-The batched form deals the replicas into concurrent groups, each sweeping on
-its own stream, so the sweep kernel's launches of one kind (A or B) run as a
-wave of concurrent dispatches that together update half a sweep of every
-replica.  The roofline's unit is that launch wave: its algorithmic operations
-over its average duration, i.e. the timed region (HIP events on the
-context's stream, which forks to and joins from the group streams) divided by
-the waves in it.  The same form run as one launch chain over all replicas,
-timed the same way, gives the sweep kernel's own per-launch time beside it.
+Roofline: algorithmic bytes (each updated spin read and written once per
+sweep: 2 B int8, 0.25 B bit-packed) of one sweep-kernel launch over its
+average duration.  A launch (A or B) updates half a sweep of every replica.
+The per-launch time is taken from the form run as one launch chain over all
+replicas (graph replay, HIP events on the context's stream, timed region
+over its launches), the configuration a rocprofv3 kernel trace times the
+same way; the batched form's concurrent group dispatches give the
+`grouped_wave` figure beside it.
 """
 from __future__ import annotations
 
@@ -43,29 +46,11 @@ TEMPS = (2.0, 3.0, 4.0)
 H1 = 0.55
 SEED = 14115588
 
-# MI355X: 256 CUs x 4 SIMDs at 2.4 GHz.  A SIMD issues one wave64 VALU
-# instruction per 4 cycles (16 lanes per clock: 39.3 T lane-ops/s), and a
-# second one from another wave in the same 4 cycles when both are simple
-# 32-bit operations (32 lanes per clock: 78.6 T lane-ops/s, the 157.3 TFLOP/s
-# fp32 vector rate with an FMA counted twice); a 64-bit integer product
-# (multiply-hi/lo) takes a whole issue slot.  HBM3E peak 8 TB/s.
-VALU32_PEAK = 256 * 4 * 32 * 2.4e9
-VALU64_PEAK = 256 * 4 * 16 * 2.4e9
-SINGLE_ISSUE_PEAK = VALU64_PEAK   # every instruction in its own issue slot
+# MI355X HBM3E peak, 8 TB/s
 HBM_PEAK_GBS = 8000.0
-# algorithmic integer operations per spin update: Philox4x32-10 gives four
-# words for 10 rounds x (2 multiply-hi/lo + 2 three-input xor), i.e. 5 products
-# and 5 xors per update; the Metropolis test adds 7 (5 adds for the
-# six-neighbour sum, 1 compare against the tabulated threshold, 1 select of the
-# flip).  The ALU roofline is that mix at the two issue rates, an upper bound:
-# the products and the three-input xors of Philox do not dual-issue in
-# practice, so the single-issue rate is reported beside it.
-OPS64, OPS32 = 5, 12
-OPS_PER_UPDATE = OPS64 + OPS32
-PEAK_UPDATES = 1.0 / (OPS64 / VALU64_PEAK + OPS32 / VALU32_PEAK)   # updates per second
-ALU_PEAK_TOPS = OPS_PER_UPDATE * PEAK_UPDATES / 1e12
 BYTES_PER_UPDATE = {"int8": 2.0, "bitpack": 0.25}   # each spin read and written once per sweep
 PROFILE_TRAFFIC = os.path.join(ROOT, "profiles", "traffic_sweep_kernel_160x480x600x3.md")
+PROFILE_VALU = os.path.join(ROOT, "profiles", "valu_sweep_kernel_160x480x600x3.md")
 KERNEL_SOURCE = os.path.join(ROOT, "paper_1411_5588_amd", "csrc", "islf_kernels.hip")
 
 
@@ -81,7 +66,11 @@ def parse():
     ap.add_argument("--fmt", choices=["int8", "bitpack"], default="bitpack")
     ap.add_argument("--no-extras", action="store_true", help="skip the other forms and formats")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
-    ap.add_argument("--cpu-sweeps", type=int, default=3)
+    ap.add_argument("--cpu-sweeps", type=int, default=10)
+    ap.add_argument("--no-configs", action="store_true",
+                    help="skip the batched-TI, uneven-autotuned and serving configurations")
+    ap.add_argument("--serve-requests", type=int, default=100,
+                    help="requests of the serving figure in the default run")
     ap.add_argument("--serve", type=int, default=0, metavar="N",
                     help="instead: the serving workload, N Poisson requests (20/s, log-uniform sizes)")
     ap.add_argument("--serve-budget-mib", type=int, default=256)
@@ -99,22 +88,33 @@ def replicas(islf, n=None):
                          seed=SEED + i, replica=i, init=islf.INIT_RANDOM) for i in range(n)]
 
 
-def run_form(islf, torch, form, fmt, steps, warmup, chunk, n_reps=None, groups=0):
+def run_form(islf, torch, form, fmt, steps, warmup, chunk, n_reps=None, groups=0, reps=None, autotune=0):
+    """Times `steps` sweeps of a batch in one execution form: graph replays of
+    `chunk` sweeps (plus eager sweeps for a remainder), after one untimed
+    replay of the same graph and the rest of the warm-up.  HIP events on the
+    context's stream bracket the timed region (the group streams fork from
+    and join back to it inside it)."""
     mode = {"persistent": islf.EXEC_PERSISTENT, "batched": islf.EXEC_BATCHED, "plain": islf.EXEC_PLAIN}[form]
     f = {"int8": islf.INT8, "bitpack": islf.BITPACK}[fmt]
-    reps = replicas(islf, n_reps)
-    ctx = islf.Context(reps, spin_format=f, obs_capacity=steps + warmup + 64, exec_mode=mode)
+    reps = replicas(islf, n_reps) if reps is None else reps
+    chunk = max(1, min(chunk, steps))
+    n_warm = max(1, warmup // chunk)
+    warm_rest = max(0, warmup - n_warm * chunk)
+    ctx = islf.Context(reps, spin_format=f, obs_capacity=steps + n_warm * chunk + warm_rest + 64, exec_mode=mode)
     try:
-        chunk = max(1, min(chunk, steps))
+        tuned = 0.0
+        if autotune:
+            t = time.perf_counter()
+            ctx.autotune(autotune)
+            tuned = time.perf_counter() - t
         if groups:
             ctx.set_groups(groups)
         ctx.capture(chunk)
-        # warm-up: replays of the same graph (its first launch is slower), then
-        # eager sweeps for the remainder
-        if warmup // chunk:
-            ctx.replay(warmup // chunk)
-        if warmup % chunk:
-            ctx.sweep(warmup % chunk)
+        # warm-up: always one untimed replay of the graph (the first replay of
+        # a new graph is slower), then eager sweeps for the remainder
+        ctx.replay(n_warm)
+        if warm_rest:
+            ctx.sweep(warm_rest)
         n_launch = steps // chunk
         rest = steps - n_launch * chunk
         s = ctx.stream
@@ -129,12 +129,22 @@ def run_form(islf, torch, form, fmt, steps, warmup, chunk, n_reps=None, groups=0
         t1.record(s)
         torch.cuda.synchronize()
         total_ms = t0.elapsed_time(t1)
+        done = n_warm * chunk + warm_rest + steps
         for i in range(len(reps)):
-            assert ctx.sweep_count(i) == warmup + steps
-        return dict(ms_per_sweep=total_ms / steps, sweeps_per_launch=chunk, launches=n_launch,
-                    groups=ctx.get_groups() if form == "batched" else 1, grid=ctx.get_grid())
+            assert ctx.sweep_count(i) == done
+        out = dict(ms_per_sweep=total_ms / steps, sweeps_per_launch=chunk, launches=n_launch,
+                   warmup_sweeps=done - steps, groups=ctx.get_groups() if form == "batched" else 1,
+                   grid=ctx.get_grid(), sites=sum(r.N for r in reps), ctx_means=None)
+        if autotune:
+            out["autotune_s"] = round(tuned, 2)
+        out["ctx_means"] = ctx.means(done - steps, steps)
+        return out
     finally:
         ctx.close()
+
+
+def rate(run):
+    return run["sites"] / (run["ms_per_sweep"] * 1e6)
 
 
 def layer_profile_rate(islf, torch, calls=20):
@@ -204,19 +214,110 @@ def kernel_code_hash():
     return hashlib.sha256("\n".join(lines).encode()).hexdigest()[:16]
 
 
-def committed_traffic(fmt):
-    """HBM bytes per launch wave of the sweep kernel (the A or B dispatches of
-    all groups, half a sweep of every replica) from the committed counter
+def committed_figure(path, key):
+    """A machine-readable figure `key: value` from a committed counter
     summary, or None when the kernel code has changed since it was taken."""
     try:
-        text = open(PROFILE_TRAFFIC).read()
+        text = open(path).read()
     except OSError:
         return None
     m = re.search(r"kernel_code_sha256_16:\s*([0-9a-f]+)", text)
     if not m or m.group(1) != kernel_code_hash():
         return None
-    m = re.search(rf"traffic_bytes_per_wave\[{fmt}\]:\s*([0-9.eE+]+)", text)
+    m = re.search(re.escape(key) + r":\s*([0-9.eE+-]+)", text)
     return float(m.group(1)) if m else None
+
+
+def committed_traffic(fmt):
+    """HBM bytes (FETCH_SIZE + WRITE_SIZE, copy-calibrated) per sweep-kernel
+    launch of the one-launch-chain form (half a sweep of every replica)."""
+    return committed_figure(PROFILE_TRAFFIC, f"traffic_bytes_per_launch[{fmt}]")
+
+
+def committed_valu(fmt):
+    """Counter-based VALU figures of the same launches: the share of the
+    dispatch's SIMD issue slots that issued a VALU instruction
+    (SQ_ACTIVE_INST_VALU over GRBM_GUI_ACTIVE cycles) and VALU lane-ops per
+    update."""
+    f = committed_figure(PROFILE_VALU, f"valu_issue_frac[{fmt}]")
+    if f is None:
+        return None
+    return {"issue_frac": f, "lane_ops_per_update": committed_figure(PROFILE_VALU, f"valu_lane_ops_per_update[{fmt}]"),
+            "source": os.path.relpath(PROFILE_VALU, ROOT)}
+
+
+def ti_replicas(islf):
+    """The batched thermodynamic-integration batch: 64 replicas of
+    40 x 120 x 120 along the surface-field path h1 = r/63, hn = -h1, T = 3."""
+    return [islf.Replica(40, 120, 120, islf.GAPBC, J=1.0, beta=1.0 / 3.0, H=0.0, h1=r / 63.0, hn=-r / 63.0,
+                         seed=SEED + r, replica=r, init=islf.INIT_RANDOM) for r in range(64)]
+
+
+def uneven_replicas(islf):
+    """96 replicas, round-robin over Lx in {20, 40, 80} x Ly = Lz in
+    {64, 128, 256}, T in {2, 2.5, 3, 3.5, 4}, |h1| in {0.25, 0.5, 0.75}."""
+    out = []
+    for r in range(96):
+        c = r % 9
+        Lx = (20, 40, 80)[c // 3]
+        L = (64, 128, 256)[c % 3]
+        T = (2.0, 2.5, 3.0, 3.5, 4.0)[(r // 9) % 5]
+        h = (0.25, 0.5, 0.75)[(r // 45) % 3]
+        out.append(islf.Replica(Lx, L, L, islf.GAPBC, J=1.0, beta=1.0 / T, H=0.0, h1=h, hn=-h,
+                                seed=SEED + 1000 + r, replica=r, init=islf.INIT_RANDOM))
+    return out
+
+
+def config_figures(islf, torch, steps, warmup, chunk, serve_requests, serve_budget_mib):
+    """The batched configurations beside the headline: updates/ns per form
+    and format, the field-path integral of the TI batch, serving latency."""
+    import numpy as np
+
+    out = {}
+    st, wu = min(steps, 100), min(warmup, 50)
+    ti = {}
+    for form, fmt in (("batched", "bitpack"), ("batched", "int8"), ("persistent", "bitpack"),
+                      ("persistent", "int8")):
+        r = run_form(islf, torch, form, fmt, st, wu, min(chunk, 50), reps=ti_replicas(islf))
+        ti[f"{form}_{fmt}"] = round(rate(r), 2)
+        print(f"# TI batch {form}/{fmt}: { {k: v for k, v in r.items() if k != 'ctx_means'} }", file=sys.stderr,
+              flush=True)
+        if (form, fmt) == ("batched", "bitpack"):
+            m = r["ctx_means"]
+            h = np.arange(64) / 63.0
+            cum = islf.integrate(h, m[:, 3], m[:, 4], -1.0, 1.0, 1.0 / (120 * 120))
+            ti["delta_f1_at_h1_1"] = float(cum[-1])
+    ti["workload"] = ("64 replicas of 40x120x120 GAPBC, T=3, h1=r/63, hn=-h1, seeds 14115588+r; "
+                      f"timed over {st} sweeps; delta_f1 = trapezoid of -(m1 - mn) over h1 after the timed sweeps "
+                      "(short chains: a throughput check, not a physics result)")
+    out["ti_64x40x120x120"] = ti
+    un = {}
+    r = run_form(islf, torch, "batched", "int8", st, wu, min(chunk, 50), reps=uneven_replicas(islf), autotune=4)
+    un["batched_int8_autotuned"] = round(rate(r), 2)
+    un["autotune_s"] = r.get("autotune_s")
+    print(f"# uneven batch int8 autotuned: { {k: v for k, v in r.items() if k != 'ctx_means'} }", file=sys.stderr,
+          flush=True)
+    r = run_form(islf, torch, "batched", "bitpack", st, wu, min(chunk, 50), reps=uneven_replicas(islf))
+    un["batched_bitpack"] = round(rate(r), 2)
+    un["workload"] = (f"96 replicas, Lx in {{20,40,80}} x Ly=Lz in {{64,128,256}}, T in {{2,2.5,3,3.5,4}}, "
+                      f"|h1| in {{0.25,0.5,0.75}}, 125,583,360 sites; timed over {st} sweeps")
+    out["uneven_96"] = un
+    if serve_requests:
+        from paper_1411_5588_amd import serving
+        reqs = serving.poisson_workload(serve_requests, rate=20.0)
+        srv = serving.Server(budget_bytes=serve_budget_mib << 20, max_slots=64, spin_format=islf.BITPACK,
+                             max_step=50, obs_capacity=5000, realtime=True)
+        try:
+            srv.run(reqs)
+        finally:
+            srv.close()
+        sm = serving.summary(reqs, srv.wall_s, srv.busy_s)
+        out["serving"] = {k: round(v, 4) for k, v in sm.items()}
+        out["serving"]["workload"] = (f"{serve_requests} requests, Poisson 20/s, sites log-uniform on [1e5, 4.6e7], "
+                                      f"T~U[2,4.2], h1~U[0.1,1], hn=-h1, sweeps~U{{500..5000}}, bit-packed, "
+                                      f"memory budget {serve_budget_mib} MiB, at most 64 slots")
+        print(f"# serving: {out['serving']}", file=sys.stderr, flush=True)
+    return out
 
 
 def cpu_baseline(n_sweeps, max_threads=16):
@@ -315,64 +416,70 @@ def main():
     Lx, Ly, Lz = SHAPE
     N = Lx * Ly * Lz
     n_reps = len(TEMPS)
-    updates_per_sweep = N * n_reps
+
+    def brief(r):
+        return {k: v for k, v in r.items() if k != "ctx_means"}
 
     main_run = run_form(islf, torch, args.form, args.fmt, args.steps, args.warmup, args.chunk, groups=args.groups)
-    print(f"# {args.form}/{args.fmt}: {main_run}", file=sys.stderr, flush=True)
-    value = updates_per_sweep / (main_run["ms_per_sweep"] * 1e6)
-    # the same form as one launch chain over all replicas, timed the same way
+    print(f"# {args.form}/{args.fmt}: {brief(main_run)}", file=sys.stderr, flush=True)
+    value = rate(main_run)
+    # the same form as one launch chain over all replicas, timed the same way:
+    # its launches run one after another, so timed region / launches is the
+    # sweep kernel's own average launch duration
     if main_run["groups"] == 1:
         chain_run = main_run
     else:
         chain_run = run_form(islf, torch, args.form, args.fmt, min(args.steps, 400), min(args.warmup, 100),
                              args.chunk, groups=1)
-        print(f"# {args.form}/{args.fmt} one launch chain: {chain_run}", file=sys.stderr, flush=True)
+        print(f"# {args.form}/{args.fmt} one launch chain: {brief(chain_run)}", file=sys.stderr, flush=True)
 
     forms = {}
     if not args.no_extras:
-        for form, fmt in (("plain", "bitpack"), ("batched", "int8"), ("plain", "int8"), ("persistent", "bitpack"),
+        other = "int8" if args.fmt == "bitpack" else "bitpack"
+        for form, fmt in (("batched", other), ("plain", "bitpack"), ("plain", "int8"), ("persistent", "bitpack"),
                           ("persistent", "int8")):
             if (form, fmt) == (args.form, args.fmt):
                 continue
-            r = run_form(islf, torch, form, fmt, min(args.steps, 100), min(args.chunk, 50), min(args.chunk, 50))
-            forms[f"{form}_{fmt}"] = round(updates_per_sweep / (r["ms_per_sweep"] * 1e6), 2)
-            print(f"# {form}/{fmt}: {r}", file=sys.stderr, flush=True)
+            r = run_form(islf, torch, form, fmt, min(args.steps, 100), min(args.warmup, 50), min(args.chunk, 50))
+            forms[f"{form}_{fmt}"] = round(rate(r), 2)
+            print(f"# {form}/{fmt}: {brief(r)}", file=sys.stderr, flush=True)
         # a batch larger than the 256 MB last-level cache: 8 int8 replicas, 369 MB of spins
-        r = run_form(islf, torch, "batched", "int8", min(args.steps, 50), min(args.chunk, 50), min(args.chunk, 50),
+        r = run_form(islf, torch, "batched", "int8", min(args.steps, 50), min(args.warmup, 50), min(args.chunk, 50),
                      n_reps=8)
-        forms["batched_int8_8x46M_369MB"] = round(8 * N / (r["ms_per_sweep"] * 1e6), 2)
-        print(f"# batched/int8 x8: {r}", file=sys.stderr, flush=True)
+        forms["batched_int8_8x46M_369MB"] = round(rate(r), 2)
+        print(f"# batched/int8 x8: {brief(r)}", file=sys.stderr, flush=True)
+
+    configs = None
+    if not args.no_configs:
+        configs = config_figures(islf, torch, args.steps, args.warmup, args.chunk, args.serve_requests,
+                                 args.serve_budget_mib)
 
     # dominant kernel: the sweep kernel.  Its A and B launches of one sweep
     # together update every site of every replica once (A: phase 0 and the
-    # previous sweep's phase 3, B: phases 1 and 2), so a launch wave (the A or
-    # B dispatches of all concurrent groups) updates half a sweep of every
-    # replica; its average duration is the timed region over its 2 x steps
-    # waves (the region also holds one closing launch and fold per graph
-    # launch, so this slightly overstates the wave time)
-    updates_per_wave = n_reps * N / 2
+    # previous sweep's phase 3, B: phases 1 and 2), so one launch updates half
+    # a sweep of every replica; the one-chain timed region over its 2 x steps
+    # launches is the average launch duration (the region also holds one
+    # closing launch and fold per graph launch, so this slightly overstates it)
+    bpu = BYTES_PER_UPDATE[args.fmt]
+    updates_per_launch = n_reps * N / 2
+    alg_bytes = bpu * updates_per_launch
+    launch_ms = chain_run["ms_per_sweep"] / 2
+    achieved = alg_bytes / (launch_ms * 1e-3) / 1e9
     wave_ms = main_run["ms_per_sweep"] / 2
-    achieved_tops = OPS_PER_UPDATE * updates_per_wave / (wave_ms * 1e-3) / 1e12
-    # one launch chain over all replicas: its launches run one after another,
-    # so the same quotient is the sweep kernel's own per-launch time
-    chain_ms = chain_run["ms_per_sweep"] / 2
-    chain_tops = OPS_PER_UPDATE * updates_per_wave / (chain_ms * 1e-3) / 1e12
-    traffic = committed_traffic(args.fmt)
-    alg_gbs = BYTES_PER_UPDATE[args.fmt] * updates_per_wave / (wave_ms * 1e-3) / 1e9
-    roofline = {"bound": "alu", "achieved": round(achieved_tops, 2), "peak": round(ALU_PEAK_TOPS, 1),
-                "unit": "T int-op/s", "frac": round(achieved_tops / ALU_PEAK_TOPS, 4), "traffic": traffic,
-                "kernel": "k_sweep (A and B launches)",
-                "peak_basis": f"per update {OPS64} 64-bit products at {VALU64_PEAK / 1e12:.1f} T/s + {OPS32} 32-bit "
-                              f"ops at {VALU32_PEAK / 1e12:.1f} T/s = {PEAK_UPDATES / 1e9:.0f} updates/ns",
-                "launch_unit": f"wave of {main_run['groups']} concurrent group dispatches of "
-                               f"{main_run['grid']} workgroups, half a sweep of every replica",
-                "wave_ms": round(wave_ms, 5), "ops_per_update": OPS_PER_UPDATE,
-                "single_chain": {"kernel_ms": round(chain_ms, 5), "workgroups": chain_run["grid"],
-                                 "achieved": round(chain_tops, 2), "frac": round(chain_tops / ALU_PEAK_TOPS, 4)},
-                "single_issue": {"peak": round(SINGLE_ISSUE_PEAK / 1e12, 1),
-                                 "frac": round(achieved_tops * 1e12 / SINGLE_ISSUE_PEAK, 4)},
-                "hbm_view": {"algorithmic_GBs": round(alg_gbs, 1), "peak_GBs": HBM_PEAK_GBS,
-                             "frac": round(alg_gbs / HBM_PEAK_GBS, 4)}}
+    wave_gbs = alg_bytes / (wave_ms * 1e-3) / 1e9
+    roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": committed_traffic(args.fmt),
+                "kernel": "k_sweep (A and B launches), one launch over all three replicas",
+                "launch_ms": round(launch_ms, 5), "workgroups": chain_run["grid"],
+                "algorithmic_bytes_per_launch": alg_bytes, "bytes_per_update": bpu,
+                "roofline_updates_per_ns": HBM_PEAK_GBS / bpu,
+                "grouped_wave": {"wave_ms": round(wave_ms, 5), "achieved": round(wave_gbs, 1),
+                                 "frac": round(wave_gbs / HBM_PEAK_GBS, 4),
+                                 "unit": f"wave of {main_run['groups']} concurrent group dispatches of "
+                                         f"{main_run['grid']} workgroups (the headline form), half a sweep of "
+                                         f"every replica"},
+                "valu": committed_valu(args.fmt),
+                "limiter": "VALU issue: Philox4x32-10 costs 5 64-bit products and 5 xors per update"}
 
     prof = layer_profile_rate(islf, torch)
     print(f"# layer profile: {prof}", file=sys.stderr, flush=True)
@@ -389,9 +496,11 @@ def main():
                                f"{list(TEMPS)}, {args.fmt} spins, {args.form} form, "
                                f"{main_run['sweeps_per_launch']} sweeps per graph launch",
                    "sites_per_replica": N, "replicas": n_reps, "form": args.form, "spin_format": args.fmt,
-                   "groups": main_run["groups"], "workgroups_per_launch": main_run["grid"]},
-        "forms": forms,
+                   "groups": main_run["groups"], "workgroups_per_launch": main_run["grid"],
+                   "warmup_sweeps_run": main_run["warmup_sweeps"]},
         "roofline": roofline,
+        "forms": forms,
+        "configs": configs,
         "layer_profile": prof,
         "host_io": hio,
         "cpu_baseline": cpu,

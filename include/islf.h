@@ -148,7 +148,17 @@ islf_status islf_set_exec(islf_ctx *ctx, int32_t exec_mode);
 /* Enqueues n_sweeps sweeps of every live replica on the context's stream and
  * returns without waiting.  Per sweep the per-flip changes of (B, M, M1, Mn)
  * are reduced inside the update kernels and one record is stored per replica.
- * Errors: ERANGE if a replica's sweep index would pass 2^32-1, EDEVICE. */
+ * Errors: ERANGE if a replica's sweep index would pass 2^32-1, EDEVICE,
+ * ESTATE if a live replica is marked failed (below).
+ *
+ * Failure of a persistent launch: its grid barriers wait a bounded time; a
+ * block that gives up raises an error word and every block of the launch
+ * then stops at its next barrier, leaving the sweeps half done.  The next
+ * call that reads results (measure, sweep_count, get_spins, recompute,
+ * record_energy, means) returns EDEVICE and marks every live replica failed;
+ * from then on calls on a failed replica (and sweeps, graph capture and
+ * replay of a context holding one) return ESTATE until islf_set_spins
+ * restarts it at sweep 0 or it is retired. */
 islf_status islf_sweep(islf_ctx *ctx, uint32_t n_sweeps);
 
 /* Sweep index of the replica = number of sweeps it has completed (synchronises). */
@@ -235,9 +245,17 @@ islf_status islf_footprint_bytes(const islf_replica_desc *desc, int32_t spin_for
  * Synchronises.  Errors: EINVAL, ERANGE, ENOMEM. */
 islf_status islf_batch_add(islf_ctx *ctx, const islf_replica_desc *desc, int32_t *slot);
 
-/* Retires a replica: its slot stops sweeping and its memory is released
- * (or kept for reuse).  Synchronises.  Errors: ERANGE (slot not live). */
+/* Retires a replica: its slot stops sweeping and its device memory (spins,
+ * records, accumulators) is released, so that the memory a context holds
+ * follows its live replicas.  Synchronises.  Errors: ERANGE (slot not live). */
 islf_status islf_batch_retire(islf_ctx *ctx, int32_t slot);
+
+/* Device bytes the context holds now: *total over every allocation
+ * (replica blocks, descriptor tables, launch plans, work lists, sync words),
+ * *replica_bytes (optional) over the replicas' own blocks (spins, record
+ * ring, accumulators), the part islf_footprint_bytes prices per replica.
+ * Host only, no synchronisation.  Errors: EINVAL (NULL context or total). */
+islf_status islf_device_bytes(const islf_ctx *ctx, uint64_t *total, uint64_t *replica_bytes);
 
 /* Records k_sweeps sweeps of the current batch (in the current execution
  * form) as HIP graphs: one graph, or with concurrent replica groups
@@ -317,13 +335,17 @@ islf_status islf_get_groups(const islf_ctx *ctx, int32_t *groups);
  * slot of the sweep kernels on the device for one launch chain; concurrent
  * replica groups of the batched form together get 3/2 per slot, split
  * evenly (at least 64 per group); a nonzero value
- * applies to every group's launches.  islf_get_grid reports the count of one
+ * applies to every group's launches.  For the persistent form it is the
+ * grid of the cooperative launch, which must not exceed the co-residency
+ * bound the library computes for the persistent kernel on the device (the
+ * smaller of the runtime's occupancy and a count from the kernel's registers,
+ * LDS and the CU's thread slots, times the CUs); its default is one
+ * workgroup per CU below that bound.  islf_get_grid reports the count of one
  * launch of the context's form: of one group's launch with several groups;
- * for a persistent context, the grid of its cooperative launch (set by the
- * device, one workgroup per CU below the persistent kernel's theoretical
- * occupancy, not by islf_set_grid).  Every choice computes the same result.
- * Changing it invalidates a captured graph.  Errors: EINVAL (NULL context,
- * workgroups < 0 or > 2^20). */
+ * for a persistent context, the grid of its cooperative launch.  Every choice
+ * computes the same result.  Changing it invalidates a captured graph.
+ * Errors: EINVAL (NULL context, workgroups < 0 or > 2^20), ERANGE (a
+ * persistent context, or a persistent sweep, with a grid above the bound). */
 islf_status islf_set_grid(islf_ctx *ctx, int32_t workgroups);
 islf_status islf_get_grid(const islf_ctx *ctx, int32_t *workgroups);
 

@@ -351,14 +351,23 @@ void oracle_layer_profile(const or_lattice *L, const int8_t *s, int64_t *out)
     }
 }
 
-/* E = -J B - H M - h1 M1 - hn Mn (Eq. 1), evaluated left to right in FP64. */
+/* E = -J B - H M - h1 M1 - hn Mn (Eq. 1), evaluated left to right in FP64,
+ * at observables given as doubles: an exact record, or the means of records
+ * (the energy is linear in them, so the mean energy is E at the means). */
+double oracle_energy_at(double J, double H, double h1, double hn, const double obs[4])
+{
+    double e = -J * obs[0];
+    e = e - H * obs[1];
+    e = e - h1 * obs[2];
+    e = e - hn * obs[3];
+    return e;
+}
+
+/* The same for one integer record (B, M, M1, Mn). */
 double oracle_energy(double J, double H, double h1, double hn, const int64_t obs[4])
 {
-    double e = -J * (double)obs[0];
-    e = e - H * (double)obs[1];
-    e = e - h1 * (double)obs[2];
-    e = e - hn * (double)obs[3];
-    return e;
+    const double d[4] = {(double)obs[0], (double)obs[1], (double)obs[2], (double)obs[3]};
+    return oracle_energy_at(J, H, h1, hn, d);
 }
 
 /* Run sweeps t0 .. t0+n-1, recording (B, M, M1, Mn) after each one. */

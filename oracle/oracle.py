@@ -73,6 +73,8 @@ def lib():
         L.oracle_observables.argtypes = [vp, vp, vp]
         L.oracle_energy.restype = dbl
         L.oracle_energy.argtypes = [dbl, dbl, dbl, dbl, vp]
+        L.oracle_energy_at.restype = dbl
+        L.oracle_energy_at.argtypes = [dbl, dbl, dbl, dbl, vp]
         L.oracle_run.argtypes = [vp, vp, u32, u32, vp]
         L.oracle_mean.restype = dbl
         L.oracle_mean.argtypes = [vp, i64, i64]
@@ -101,8 +103,14 @@ def threshold_of_de(beta: float, dE: float) -> int:
 
 
 def energy(J, H, h1, hn, obs) -> float:
-    o = np.ascontiguousarray(obs, dtype=np.int64)
-    return float(lib().oracle_energy(J, H, h1, hn, _ptr(o)))
+    """Eq. 1 at one record (B, M, M1, Mn): an integer record, or (floats)
+    the means of records."""
+    a = np.asarray(obs)
+    if np.issubdtype(a.dtype, np.integer):
+        o = np.ascontiguousarray(a, dtype=np.int64)
+        return float(lib().oracle_energy(J, H, h1, hn, _ptr(o)))
+    o = np.ascontiguousarray(a, dtype=np.float64)
+    return float(lib().oracle_energy_at(J, H, h1, hn, _ptr(o)))
 
 
 def integrate(h, m1, mn, c1=-1.0, cn=1.0, norm=1.0) -> np.ndarray:

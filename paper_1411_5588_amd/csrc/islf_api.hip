@@ -12,6 +12,7 @@
 
 #include <algorithm>
 #include <string>
+#include <unordered_map>
 #include <vector>
 
 #include "islf_internal.h"
@@ -189,6 +190,7 @@ struct Replica {
     void *mem = nullptr;     // spins | records | accumulators
     size_t mem_bytes = 0;
     uint64_t t_host = 0;     // sweeps issued so far
+    bool failed = false;     // its chain was cut short by a failed persistent launch
     int tile = 0;
     RepDesc d{};
     std::vector<Entry> main, slab;
@@ -217,7 +219,8 @@ struct islf_ctx {
     int resident_slots = 0;    // workgroups of the sweep kernels resident at once on the device
     int sweep_slots = 0;       // default workgroups per sweep launch (2 per resident slot)
     int grid_override = 0;     // workgroups per batched / plain launch (0: sweep_slots)
-    int persistent_grid = 0;   // co-resident blocks of the persistent kernel
+    int persistent_grid = 0;   // workgroups of the persistent kernel's cooperative launch
+    int persistent_bound = 0;  // co-residency bound computed for it on this device
 
     std::vector<Replica> reps;
     int slot_capacity = 0;
@@ -248,20 +251,36 @@ struct islf_ctx {
     std::vector<hipGraphExec_t> graph_execs;
     uint32_t graph_sweeps = 0;
     bool graph_valid = false;
+
+    // device bytes the context holds, by allocation
+    std::unordered_map<void *, size_t> alloc_bytes;
+    size_t dev_bytes = 0;
 };
+
+static islf_status check_intact(islf_ctx *c, int rep);
+static islf_status check_none_failed(const islf_ctx *c);
 
 static void *dev_alloc(islf_ctx *c, size_t bytes)
 {
     if (bytes == 0) bytes = 256;
-    if (c->alloc) return c->alloc(bytes, c->user);
     void *p = nullptr;
-    if (hipMalloc(&p, bytes) != hipSuccess) return nullptr;
+    if (c->alloc) p = c->alloc(bytes, c->user);
+    else if (hipMalloc(&p, bytes) != hipSuccess) p = nullptr;
+    if (p) {
+        c->alloc_bytes[p] = bytes;
+        c->dev_bytes += bytes;
+    }
     return p;
 }
 
 static void dev_free(islf_ctx *c, void *p)
 {
     if (!p) return;
+    auto it = c->alloc_bytes.find(p);
+    if (it != c->alloc_bytes.end()) {
+        c->dev_bytes -= it->second;
+        c->alloc_bytes.erase(it);
+    }
     if (c->free_fn) c->free_fn(p, c->user);
     else (void)hipFree(p);
 }
@@ -690,7 +709,11 @@ static islf_status prepare_plans(islf_ctx *c, int exec)
     if (exec == ISLF_EXEC_PERSISTENT && !c->persistent.valid) {
         std::vector<Entry> S, M;
         lists(c->live, S, M);
-        return build_plan(c, c->persistent, S, M, c->persistent_grid, kPersistentTaper);
+        const int grid = c->grid_override ? c->grid_override : c->persistent_grid;
+        if (grid > c->persistent_bound)
+            return fail(ISLF_ERANGE, "persistent grid %d exceeds the co-residency bound %d of this device", grid,
+                        c->persistent_bound);
+        return build_plan(c, c->persistent, S, M, grid, kPersistentTaper);
     }
     if (exec == ISLF_EXEC_PLAIN) {
         if (c->plain.size() < c->reps.size()) c->plain.resize(c->reps.size());
@@ -796,6 +819,26 @@ static void destroy_ctx(islf_ctx *c)
     delete c;
 }
 
+// Workgroups of a 256-thread kernel that can be resident on one CU at once,
+// the smaller of the runtime's occupancy answer and a count from the
+// kernel's own resources: a workgroup is four wave64s, one per SIMD, so a
+// SIMD's 512 VGPRs per lane (allocated in granules of 8) bound the
+// workgroups per CU, and so do the CU's thread slots and LDS.
+static int coresident_per_cu(const void *kernel, const hipDeviceProp_t &prop)
+{
+    int rt = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&rt, kernel, kBlock, 0) != hipSuccess || rt < 1) rt = 1;
+    hipFuncAttributes a;
+    if (hipFuncGetAttributes(&a, kernel) != hipSuccess) return rt;
+    int per_cu = rt;
+    const int vgprs = std::max(1, (a.numRegs + 7) / 8 * 8);
+    per_cu = std::min(per_cu, 512 / vgprs);
+    if (prop.maxThreadsPerMultiProcessor > 0) per_cu = std::min(per_cu, prop.maxThreadsPerMultiProcessor / kBlock);
+    if (a.sharedSizeBytes > 0 && prop.maxSharedMemoryPerMultiProcessor > 0)
+        per_cu = std::min(per_cu, (int)(prop.maxSharedMemoryPerMultiProcessor / a.sharedSizeBytes));
+    return std::max(1, per_cu);
+}
+
 // ---------------------------------------------------------------------------
 // public API
 // ---------------------------------------------------------------------------
@@ -835,16 +878,15 @@ extern "C" islf_status islf_create_with_allocator(const islf_replica_desc *reps,
     // round leaves slots idle while the last workgroups finish)
     c->resident_slots = c->num_cu * per_cu_sweep;
     c->sweep_slots = 2 * c->resident_slots;
-    int per_cu = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, persistent_kernel(spin_format), kBlock, 0) != hipSuccess ||
-        per_cu < 1)
-        per_cu = 1;
-    // one slot per CU stays free: at the full theoretical occupancy (7
-    // workgroups per CU for a 72-VGPR kernel) a cooperative launch was
-    // accepted but its workgroups were not all resident at once, and the grid
-    // barrier's bounded wait expired
+    const int per_cu = coresident_per_cu(persistent_kernel(spin_format), prop);
+    c->persistent_bound = std::min(c->num_cu * per_cu, kBarrierGroup * kMaxGroups);
+    // one slot per CU stays free by default: at the full occupancy the
+    // runtime reported for an earlier build of the int8 kernel (7 workgroups
+    // per CU at 72 VGPRs) a cooperative launch was accepted but its workgroups
+    // were not all resident at once, and the grid barrier's bounded wait
+    // expired
     const int per_cu_p = per_cu > 1 ? per_cu - 1 : 1;
-    c->persistent_grid = std::min(c->num_cu * std::min(per_cu_p, 8), kBarrierGroup * kMaxGroups);
+    c->persistent_grid = std::min(c->num_cu * per_cu_p, c->persistent_bound);
     c->d_sync = (GridSync *)dev_alloc(c, sizeof(GridSync));
     c->d_scratch = (unsigned long long *)dev_alloc(c, 64 * sizeof(unsigned long long));
     if (!c->d_sync || !c->d_scratch) {
@@ -921,7 +963,8 @@ extern "C" islf_status islf_set_spins(islf_ctx *ctx, int32_t rep, const int8_t *
     Replica &R = ctx->reps[rep];
     const size_t N = (size_t)R.desc.Lx * R.desc.Ly * R.desc.Lz;
     if (!host || n != N) return fail(ISLF_EINVAL, "expected %zu spins, got %zu", N, n);
-    if (R.t_host != 0) return fail(ISLF_ESTATE, "set_spins is only valid before the first sweep");
+    if (R.t_host != 0 && !R.failed)
+        return fail(ISLF_ESTATE, "set_spins is only valid before the first sweep (or after a failed launch)");
     // +1 and -1 are the bytes 0x01 and 0xFF: (byte + 1) & 0xFD is 0 exactly for
     // them (a branch-free pass the compiler vectorises; the index of a bad
     // value is looked up only when there is one)
@@ -941,6 +984,10 @@ extern "C" islf_status islf_set_spins(islf_ctx *ctx, int32_t rep, const int8_t *
     }
     st = init_replica(ctx, rep, 3, staged);
     dev_free(ctx, staged);
+    if (st == ISLF_OK && R.failed) {
+        R.failed = false;
+        ctx->graph_valid = false;
+    }
     return st;
 }
 
@@ -951,6 +998,8 @@ extern "C" islf_status islf_get_spins(islf_ctx *ctx, int32_t rep, int8_t *host, 
     Replica &R = ctx->reps[rep];
     const size_t N = (size_t)R.desc.Lx * R.desc.Ly * R.desc.Lz;
     if (!host || n != N) return fail(ISLF_EINVAL, "expected %zu spins, got %zu", N, n);
+    st = check_intact(ctx, rep);
+    if (st != ISLF_OK) return st;
     int8_t *tmp = (int8_t *)dev_alloc(ctx, N);
     if (!tmp) return fail(ISLF_ENOMEM, "cannot allocate staging");
     hipError_t e = launch_export(ctx->d_desc, rep, (long)R.desc.Lx * R.desc.Ly, tmp, ctx->stream);
@@ -1074,6 +1123,48 @@ static islf_status enqueue_sweeps(islf_ctx *c, uint32_t n)
     return ISLF_OK;
 }
 
+// Reads the persistent kernel's error word (synchronises).  A raised word
+// means a launch gave up at a grid barrier and left its sweeps half done, so
+// every live replica is marked failed (its calls return ESTATE until
+// islf_set_spins restarts it or it is retired); the word is then cleared so
+// that later launches can run.
+static islf_status check_device_error(islf_ctx *c)
+{
+    unsigned long long err = 0;
+    HIP_TRY(hipMemcpyAsync(&err, &c->d_sync->error.v, sizeof err, hipMemcpyDeviceToHost, c->stream));
+    HIP_TRY(hipStreamSynchronize(c->stream));
+    if (err) {
+        for (int r : c->live) c->reps[r].failed = true;
+        c->graph_valid = false;
+        HIP_TRY(launch_zero((unsigned long long *)&c->d_sync->error, 16, c->stream));
+        HIP_TRY(hipStreamSynchronize(c->stream));
+        return fail(ISLF_EDEVICE, "a persistent-kernel grid barrier gave up (its workgroups were not all resident at "
+                                  "once, or the wait was cut short); every live replica is marked failed");
+    }
+    return ISLF_OK;
+}
+
+// A live replica whose chain is intact: checks the device error word, then
+// the replica's failed mark.
+static islf_status check_intact(islf_ctx *c, int rep)
+{
+    islf_status st = check_device_error(c);
+    if (st != ISLF_OK) return st;
+    if (c->reps[rep].failed)
+        return fail(ISLF_ESTATE, "replica %d was cut short by a failed persistent launch (restart it with "
+                                 "islf_set_spins or retire it)", rep);
+    return ISLF_OK;
+}
+
+static islf_status check_none_failed(const islf_ctx *c)
+{
+    for (int r : c->live)
+        if (c->reps[r].failed)
+            return fail(ISLF_ESTATE, "replica %d was cut short by a failed persistent launch (restart it with "
+                                     "islf_set_spins or retire it)", r);
+    return ISLF_OK;
+}
+
 static islf_status check_sweep_range(islf_ctx *c, uint64_t n)
 {
     for (int r : c->live)
@@ -1085,7 +1176,9 @@ static islf_status check_sweep_range(islf_ctx *c, uint64_t n)
 extern "C" islf_status islf_sweep(islf_ctx *ctx, uint32_t n_sweeps)
 {
     if (!ctx) return fail(ISLF_EINVAL, "NULL context");
-    islf_status st = prepare_plans(ctx, ctx->exec);
+    islf_status st = check_none_failed(ctx);
+    if (st != ISLF_OK) return st;
+    st = prepare_plans(ctx, ctx->exec);
     if (st != ISLF_OK) return st;
     st = check_sweep_range(ctx, n_sweeps);
     if (st != ISLF_OK) return st;
@@ -1095,30 +1188,16 @@ extern "C" islf_status islf_sweep(islf_ctx *ctx, uint32_t n_sweeps)
     return ISLF_OK;
 }
 
-static islf_status check_device_error(islf_ctx *c)
-{
-    unsigned long long err = 0;
-    HIP_TRY(hipMemcpyAsync(&err, &c->d_sync->error.v, sizeof err, hipMemcpyDeviceToHost, c->stream));
-    HIP_TRY(hipStreamSynchronize(c->stream));
-    if (err) {
-        // clear it so that the context stays usable
-        HIP_TRY(launch_zero((unsigned long long *)&c->d_sync->error, 16, c->stream));
-        HIP_TRY(hipStreamSynchronize(c->stream));
-        return fail(ISLF_EDEVICE, "a persistent-kernel barrier timed out (its workgroups were not all resident at once)");
-    }
-    return ISLF_OK;
-}
-
 extern "C" islf_status islf_sweep_count(islf_ctx *ctx, int32_t rep, uint64_t *t)
 {
     islf_status st = check_rep(ctx, rep);
     if (st != ISLF_OK) return st;
     if (!t) return fail(ISLF_EINVAL, "NULL output");
+    st = check_intact(ctx, rep);
+    if (st != ISLF_OK) return st;
     RepState s;
     HIP_TRY(hipMemcpyAsync(&s, ctx->d_state + rep, sizeof s, hipMemcpyDeviceToHost, ctx->stream));
     HIP_TRY(hipStreamSynchronize(ctx->stream));
-    st = check_device_error(ctx);
-    if (st != ISLF_OK) return st;
     if (s.t != (uint32_t)ctx->reps[rep].t_host)
         return fail(ISLF_EDEVICE, "device sweep counter %u != issued %llu", s.t,
                     (unsigned long long)ctx->reps[rep].t_host);
@@ -1144,6 +1223,8 @@ extern "C" islf_status islf_measure(islf_ctx *ctx, int32_t rep, uint64_t first, 
     if (!out) return fail(ISLF_EINVAL, "NULL output");
     st = check_records(ctx, rep, first, count);
     if (st != ISLF_OK) return st;
+    st = check_intact(ctx, rep);
+    if (st != ISLF_OK) return st;
     const Replica &R = ctx->reps[rep];
     uint32_t done = 0;
     while (done < count) {
@@ -1153,7 +1234,7 @@ extern "C" islf_status islf_measure(islf_ctx *ctx, int32_t rep, uint64_t first, 
         done += n;
     }
     HIP_TRY(hipStreamSynchronize(ctx->stream));
-    return check_device_error(ctx);
+    return ISLF_OK;
 }
 
 extern "C" islf_status islf_recompute(islf_ctx *ctx, int32_t rep, islf_obs *out)
@@ -1161,6 +1242,8 @@ extern "C" islf_status islf_recompute(islf_ctx *ctx, int32_t rep, islf_obs *out)
     islf_status st = check_rep(ctx, rep);
     if (st != ISLF_OK) return st;
     if (!out) return fail(ISLF_EINVAL, "NULL output");
+    st = check_intact(ctx, rep);
+    if (st != ISLF_OK) return st;
     const Replica &R = ctx->reps[rep];
     const size_t N = (size_t)R.desc.Lx * R.desc.Ly * R.desc.Lz;
     int8_t *tmp = (int8_t *)dev_alloc(ctx, N);
@@ -1188,6 +1271,8 @@ extern "C" islf_status islf_record_energy(islf_ctx *ctx, int32_t rep, uint64_t f
     if (!out) return fail(ISLF_EINVAL, "NULL output");
     st = check_records(ctx, rep, first, count);
     if (st != ISLF_OK) return st;
+    st = check_intact(ctx, rep);
+    if (st != ISLF_OK) return st;
     const Replica &R = ctx->reps[rep];
     double *tmp = (double *)dev_alloc(ctx, sizeof(double) * count);
     if (!tmp) return fail(ISLF_ENOMEM, "cannot allocate staging");
@@ -1211,6 +1296,10 @@ extern "C" islf_status islf_means(islf_ctx *ctx, uint64_t first, uint32_t count,
         st = check_records(ctx, r, first, count);
         if (st != ISLF_OK) return st;
     }
+    st = check_device_error(ctx);
+    if (st != ISLF_OK) return st;
+    st = check_none_failed(ctx);
+    if (st != ISLF_OK) return st;
     // live replicas only; dead slots report NaN
     const int nl = (int)ctx->live.size();
     std::vector<double> tmp_h(5 * (size_t)std::max(nl, 1));
@@ -1360,8 +1449,15 @@ extern "C" islf_status islf_batch_retire(islf_ctx *ctx, int32_t slot)
     Replica &R = ctx->reps[slot];
     R.live = false;
     R.t_host = 0;
+    R.failed = false;
+    // the slot's memory goes back to the allocator, so the device memory a
+    // context holds follows its live replicas
+    dev_free(ctx, R.mem);
+    R.mem = nullptr;
+    R.mem_bytes = 0;
+    R.main.clear();
+    R.slab.clear();
     ctx->dirty = true;
-    // the slot's memory is kept for reuse by the next admission
     return sync_tables(ctx);
 }
 
@@ -1370,7 +1466,9 @@ extern "C" islf_status islf_graph_capture(islf_ctx *ctx, uint32_t k_sweeps)
     if (!ctx) return fail(ISLF_EINVAL, "NULL context");
     if (k_sweeps < 1) return fail(ISLF_EINVAL, "k_sweeps must be >= 1");
     if (!ctx->stream) return fail(ISLF_ESTATE, "graph capture needs a non-default stream");
-    islf_status st = prepare_plans(ctx, ctx->exec);
+    islf_status st = check_none_failed(ctx);
+    if (st != ISLF_OK) return st;
+    st = prepare_plans(ctx, ctx->exec);
     if (st != ISLF_OK) return st;
     destroy_graphs(ctx);
     // concurrent groups: one graph per group, captured on the group's own
@@ -1414,7 +1512,9 @@ extern "C" islf_status islf_run_graph(islf_ctx *ctx, uint32_t n_replays)
 {
     if (!ctx) return fail(ISLF_EINVAL, "NULL context");
     if (!ctx->graph_valid || ctx->dirty) return fail(ISLF_ESTATE, "no valid captured graph");
-    islf_status st = check_sweep_range(ctx, (uint64_t)ctx->graph_sweeps * n_replays);
+    islf_status st = check_none_failed(ctx);
+    if (st != ISLF_OK) return st;
+    st = check_sweep_range(ctx, (uint64_t)ctx->graph_sweeps * n_replays);
     if (st != ISLF_OK) return st;
     const int G = (int)ctx->graph_execs.size();
     if (G > 1) HIP_TRY(fork_groups(ctx, G));
@@ -1587,6 +1687,8 @@ extern "C" islf_status islf_layer_profile(islf_ctx *ctx, int32_t rep, int32_t *d
     islf_status st = check_rep(ctx, rep);
     if (st != ISLF_OK) return st;
     if (!dev_out) return fail(ISLF_EINVAL, "NULL output");
+    if (ctx->reps[rep].failed)
+        return fail(ISLF_ESTATE, "replica %d was cut short by a failed persistent launch", rep);
     st = sync_tables(ctx);
     if (st != ISLF_OK) return st;
     const Replica &R = ctx->reps[rep];
@@ -1600,6 +1702,8 @@ extern "C" islf_status islf_layer_profile_add(islf_ctx *ctx, int32_t rep, int64_
     islf_status st = check_rep(ctx, rep);
     if (st != ISLF_OK) return st;
     if (!dev_acc) return fail(ISLF_EINVAL, "NULL accumulator");
+    if (ctx->reps[rep].failed)
+        return fail(ISLF_ESTATE, "replica %d was cut short by a failed persistent launch", rep);
     st = sync_tables(ctx);
     if (st != ISLF_OK) return st;
     const Replica &R = ctx->reps[rep];
@@ -1612,8 +1716,12 @@ extern "C" islf_status islf_set_grid(islf_ctx *ctx, int32_t workgroups)
 {
     if (!ctx) return fail(ISLF_EINVAL, "NULL context");
     if (workgroups < 0 || workgroups > (1 << 20)) return fail(ISLF_EINVAL, "invalid workgroup count %d", workgroups);
+    if (ctx->exec == ISLF_EXEC_PERSISTENT && workgroups > ctx->persistent_bound)
+        return fail(ISLF_ERANGE, "persistent grid %d exceeds the co-residency bound %d of this device", workgroups,
+                    ctx->persistent_bound);
     ctx->grid_override = workgroups;
     ctx->batched.valid = false;
+    ctx->persistent.valid = false;
     ctx->groups_valid = false;
     for (Plan &p : ctx->plain) p.valid = false;
     ctx->graph_valid = false;
@@ -1640,7 +1748,10 @@ extern "C" islf_status islf_get_groups(const islf_ctx *ctx, int32_t *groups)
 extern "C" islf_status islf_get_grid(const islf_ctx *ctx, int32_t *workgroups)
 {
     if (!ctx || !workgroups) return fail(ISLF_EINVAL, "NULL argument");
-    *workgroups = ctx->exec == ISLF_EXEC_PERSISTENT ? ctx->persistent_grid : launch_grid(ctx, ctx->exec);
+    if (ctx->exec == ISLF_EXEC_PERSISTENT)
+        *workgroups = ctx->grid_override ? ctx->grid_override : ctx->persistent_grid;
+    else
+        *workgroups = launch_grid(ctx, ctx->exec);
     return ISLF_OK;
 }
 
@@ -1698,6 +1809,8 @@ extern "C" islf_status islf_replica_means(islf_ctx *ctx, int32_t rep, uint64_t f
     if (!out) return fail(ISLF_EINVAL, "NULL output");
     st = check_records(ctx, rep, first, count);
     if (st != ISLF_OK) return st;
+    st = check_intact(ctx, rep);
+    if (st != ISLF_OK) return st;
     int *dl = (int *)dev_alloc(ctx, sizeof(int));
     double *tmp = (double *)dev_alloc(ctx, sizeof(double) * 5);
     hipError_t e = (dl && tmp) ? hipSuccess : hipErrorOutOfMemory;
@@ -1708,5 +1821,32 @@ extern "C" islf_status islf_replica_means(islf_ctx *ctx, int32_t rep, uint64_t f
     dev_free(ctx, dl);
     dev_free(ctx, tmp);
     if (e != hipSuccess) return fail(ISLF_EDEVICE, "replica means failed: %s", hipGetErrorString(e));
+    return ISLF_OK;
+}
+
+extern "C" islf_status islf_device_bytes(const islf_ctx *ctx, uint64_t *total, uint64_t *replica_bytes)
+{
+    if (!ctx || !total) return fail(ISLF_EINVAL, "NULL argument");
+    *total = (uint64_t)ctx->dev_bytes;
+    if (replica_bytes) {
+        uint64_t r = 0;
+        for (const Replica &R : ctx->reps)
+            if (R.mem) r += R.mem_bytes;
+        *replica_bytes = r;
+    }
+    return ISLF_OK;
+}
+
+// Test support, not part of the public header: raises the persistent
+// kernel's error word from the host, as a block that gave up at a grid
+// barrier would, so that the failure path can be exercised without a launch
+// that really fails.  Every block of the next persistent launch then stops
+// at its first barrier.
+extern "C" islf_status islf_testing_raise_barrier_error(islf_ctx *ctx)
+{
+    if (!ctx) return fail(ISLF_EINVAL, "NULL context");
+    const unsigned long long one = 1;
+    HIP_TRY(hipMemcpyAsync(&ctx->d_sync->error.v, &one, sizeof one, hipMemcpyHostToDevice, ctx->stream));
+    HIP_TRY(hipStreamSynchronize(ctx->stream));
     return ISLF_OK;
 }

@@ -1060,18 +1060,21 @@ __device__ __forceinline__ unsigned long long sync_load(unsigned long long *p)
     return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
-// Waits (bounded) until *p >= target; false on time-out or a raised error.
+// Waits (bounded) until *p >= target; false on time-out or a raised error
+// word (checked before the first poll too, so that once one block has given
+// up, every later barrier of the launch gives up at once).
 __device__ __forceinline__ bool sync_wait(GridSync *sync, unsigned long long *p, unsigned long long target)
 {
     unsigned long spins = 0;
-    while (sync_load(p) < target) {
+    while (true) {
+        if (sync_load(&sync->error.v)) return false;
+        if (sync_load(p) >= target) return true;
         __builtin_amdgcn_s_sleep(1);
-        if (++spins > (1ul << 22) || sync_load(&sync->error.v)) {
+        if (++spins > (1ul << 22)) {
             atomicAdd(&sync->error.v, 1ull);
             return false;
         }
     }
-    return true;
 }
 
 // Barrier number k (= passed) of a launch: two-level arrival, see GridSync.
@@ -1115,7 +1118,7 @@ __device__ bool grid_barrier(GridSync *sync, unsigned long long nblocks, unsigne
 }
 
 template <int FMT>
-__global__ __launch_bounds__(kBlock) void k_persistent(const RepDesc *__restrict__ descs,
+__global__ __launch_bounds__(kBlock, 4) void k_persistent(const RepDesc *__restrict__ descs,
                                                        RepState *__restrict__ st,
                                                        const Entry *__restrict__ items,
                                                        const int *__restrict__ first,

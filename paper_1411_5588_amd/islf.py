@@ -121,6 +121,8 @@ def lib():
             "islf_get_groups": [vp, P(i32)],
             "islf_phase_timings": [vp, u32, vp, vp],
             "islf_replica_means": [vp, i32, u64, u32, vp],
+            "islf_device_bytes": [vp, P(u64), P(u64)],
+            "islf_testing_raise_barrier_error": [vp],
         }
         for name, args in sig.items():
             f = getattr(L, name)
@@ -341,6 +343,12 @@ class Context:
         n = C.c_int32()
         _check(lib().islf_get_groups(self._h, C.byref(n)))
         return n.value
+
+    def device_bytes(self):
+        """(total, replica blocks): device bytes the context holds now."""
+        t, r = C.c_uint64(), C.c_uint64()
+        _check(lib().islf_device_bytes(self._h, C.byref(t), C.byref(r)))
+        return t.value, r.value
 
     def get_grid(self) -> int:
         n = C.c_int32()

@@ -74,7 +74,7 @@ def test_concurrent_groups_graph_and_eager(groups, grid):
 
 def test_persistent_grid_is_co_resident():
     # the cooperative launch takes one workgroup per CU below the persistent
-    # kernel's theoretical occupancy, whatever the batched grid setting
+    # kernel's co-residency bound by default; a chosen grid replaces it
     import torch
     num_cu = torch.cuda.get_device_properties(0).multi_processor_count
     ps = batch_params()
@@ -86,6 +86,8 @@ def test_persistent_grid_is_co_resident():
         grid = ctx.get_grid()
         assert grid % num_cu == 0 and 0 < grid < resident + num_cu
         ctx.set_grid(100)
+        assert ctx.get_grid() == 100
+        ctx.set_grid(0)
         assert ctx.get_grid() == grid
 
 

@@ -28,51 +28,61 @@ def params(T, replica):
                 seed=14115588 + replica, replica=replica, init=islf.INIT_RANDOM)
 
 
-@pytest.fixture(scope="module")
-def oracle_T3():
-    """Oracle: 2 sweeps of the T = 3 replica (run in a thread beside the GPU work)."""
-    p = params(3.0, 1)
-    out = {}
+TEMPS = (2.0, 3.0, 4.0)
 
-    def work():
+
+@pytest.fixture(scope="module")
+def oracle_all():
+    """Oracle: 2 sweeps of each replica of the benchmark batch (T = 2, 3, 4:
+    below and above the roughening temperature), one thread per replica,
+    running beside the GPU work."""
+    out = {i: {} for i in range(len(TEMPS))}
+
+    def work(i):
+        p = params(TEMPS[i], i)
         L = O.Lattice(p["Lx"], p["Ly"], p["Lz"], O.GAPBC, J=1.0, beta=p["beta"], h1=0.55, hn=-0.55,
                       seed=p["seed"], replica=p["replica"])
-        out["s0"] = L.s.copy()
-        out["rec"] = L.run(2)
-        out["s2"] = L.s.copy()
+        out[i]["s0"] = L.s.copy()
+        out[i]["rec"] = L.run(2)
+        out[i]["s2"] = L.s.copy()
 
-    th = threading.Thread(target=work)
-    th.start()
-    yield p, th, out
+    ths = [threading.Thread(target=work, args=(i,)) for i in range(len(TEMPS))]
+    for th in ths:
+        th.start()
+    yield ths, out
 
 
 @pytest.mark.parametrize("fmt,exec_mode,graph", [(islf.INT8, islf.EXEC_BATCHED, False),
+                                                 (islf.INT8, islf.EXEC_BATCHED, True),
                                                  (islf.BITPACK, islf.EXEC_BATCHED, False),
                                                  (islf.BITPACK, islf.EXEC_BATCHED, True),
-                                                 (islf.INT8, islf.EXEC_PERSISTENT, False),
-                                                 (islf.BITPACK, islf.EXEC_PERSISTENT, False),
-                                                 (islf.INT8, islf.EXEC_PLAIN, False)])
-def test_paper_scale_two_sweeps_bit_exact(oracle_T3, fmt, exec_mode, graph):
-    p, th, out = oracle_T3
+                                                 (islf.INT8, islf.EXEC_PERSISTENT, True),
+                                                 (islf.BITPACK, islf.EXEC_PERSISTENT, True),
+                                                 (islf.INT8, islf.EXEC_PLAIN, False),
+                                                 (islf.BITPACK, islf.EXEC_PLAIN, True)])
+def test_paper_scale_two_sweeps_bit_exact(oracle_all, fmt, exec_mode, graph):
+    ths, out = oracle_all
     # the batch the benchmark runs: T = 2, 3, 4 side by side, in its default
     # launch configuration (concurrent replica groups); graph: captured and
-    # replayed as the benchmark does
-    reps = [islf.Replica(**params(T, i)) for i, T in enumerate((2.0, 3.0, 4.0))]
+    # replayed as the benchmark does.  Every replica is compared.
+    reps = [islf.Replica(**params(T, i)) for i, T in enumerate(TEMPS)]
     with islf.Context(reps, spin_format=fmt, obs_capacity=16, exec_mode=exec_mode) as ctx:
-        s0 = ctx.get_spins(1)
+        s0 = [ctx.get_spins(i) for i in range(3)]
         if graph:
             ctx.capture(2)
             ctx.replay(1)
         else:
             ctx.sweep(2)
-        rec = ctx.measure(1, 0, 2)
-        s2 = ctx.get_spins(1)
-        rc = ctx.recompute(1)
-    th.join()
-    assert np.array_equal(s0, out["s0"])
-    assert np.array_equal(rec, out["rec"])
-    assert np.array_equal(s2, out["s2"])
-    assert np.array_equal(rc, out["rec"][-1])
+        rec = [ctx.measure(i, 0, 2) for i in range(3)]
+        s2 = [ctx.get_spins(i) for i in range(3)]
+        rc = [ctx.recompute(i) for i in range(3)]
+    for th in ths:
+        th.join()
+    for i in range(3):
+        assert np.array_equal(s0[i], out[i]["s0"]), i
+        assert np.array_equal(rec[i], out[i]["rec"]), i
+        assert np.array_equal(s2[i], out[i]["s2"]), i
+        assert np.array_equal(rc[i], out[i]["rec"][-1]), i
 
 
 def test_paper_scale_long_run_properties():

@@ -58,6 +58,41 @@ def test_each_answer_is_the_same_alone_and_in_the_mix(fmt):
     assert s["p99_latency_s"] >= s["p50_latency_s"] > 0
 
 
+def test_served_workload_sizes_alone_and_in_the_mix():
+    """Requests in the served size range (>= 1e5 sites, films of about
+    1 : 3 : 3), admitted under a budget that binds; every answer equals the
+    chain alone and the oracle's, and the replica memory the library holds
+    never exceeds the budget."""
+    reqs = serving.poisson_workload(6, rate=200.0, seed=21, min_sites=1e5, max_sites=4e5, sweep_range=(8, 24))
+    assert min(r.replica.N for r in reqs) >= 1e5
+    fmt = islf.BITPACK
+    fp = [islf.footprint_bytes(r.replica, fmt, 32) for r in reqs]
+    budget = max(fp) + int(np.median(fp))
+    srv = serving.Server(budget_bytes=budget, max_slots=8, spin_format=fmt, max_step=5, obs_capacity=32,
+                         realtime=False)
+    held = []
+    orig = srv._admit
+
+    def spy(req, now):
+        orig(req, now)
+        held.append(srv.ctx.device_bytes()[1])
+    srv._admit = spy
+    try:
+        srv.run(reqs)
+    finally:
+        srv.close()
+    assert max(held) <= budget
+    assert any(r.admitted > r.arrival for r in reqs)   # admission had to wait
+    outs = parallel_map(lambda r: oracle_trajectory(params_of(r.replica), r.sweeps)[1], reqs)
+    for r, rec in zip(reqs, outs):
+        with islf.Context([r.replica], spin_format=fmt, obs_capacity=32) as ctx:
+            ctx.sweep(r.sweeps)
+            alone = ctx.replica_means(0, 0, r.sweeps)
+        assert np.array_equal(alone, r.means), r.rid
+        assert np.array_equal(rec[-1], r.last), r.rid
+        assert r.means[3] == O.mean(rec, 2) and r.means[4] == O.mean(rec, 3)
+
+
 def test_admission_respects_budget_and_slots():
     reqs = small_workload(10, seed=3)
     fp = [islf.footprint_bytes(r.replica, islf.BITPACK, 64) for r in reqs]
@@ -70,6 +105,8 @@ def test_admission_respects_budget_and_slots():
         orig(req, now)
         peak.append(srv.used)
         assert srv.used <= srv.budget
+        # the replica blocks the library really holds stay within the budget
+        assert srv.ctx.device_bytes()[1] <= srv.budget
     srv._admit = spy
     try:
         srv.run(reqs)

@@ -116,3 +116,18 @@ def test_spin_and_field_reversal(ybc):
     for _ in range(50):
         s = np.ascontiguousarray(rng.choice(np.array([-1, 1], dtype=np.int8), size=L.N))
         assert L.energy(L.observables(s)) == R.energy(R.observables(-s))
+
+
+def test_energy_at_means_is_the_mean_energy():
+    """The energy is linear in (B, M, M1, Mn): Eq. 1 at the mean record equals
+    the mean of the records' energies (up to rounding)."""
+    rng = np.random.default_rng(19)
+    for _ in range(20):
+        J, H, h1, hn = rng.normal(size=4)
+        rec = rng.integers(-50000, 50000, size=(400, 4), dtype=np.int64)
+        es = np.array([O.energy(J, H, h1, hn, r) for r in rec])
+        m = rec.astype(np.float64).mean(axis=0)
+        e_at = O.energy(J, H, h1, hn, m)
+        assert e_at == pytest.approx(es.mean(), rel=1e-12, abs=1e-9)
+        # an integer record given as floats gives the same value
+        assert O.energy(J, H, h1, hn, rec[0].astype(np.float64)) == es[0]
