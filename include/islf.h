@@ -190,6 +190,21 @@ islf_status islf_record_energy(islf_ctx *ctx, int32_t rep, uint64_t first, uint3
  * synchronises.  Errors: ERANGE if a replica lacks a requested record. */
 islf_status islf_means(islf_ctx *ctx, uint64_t first, uint32_t count, double *out);
 
+/* The means of islf_means, with the same results and layout, for callers
+ * that cannot allocate device memory (code between graph captures, tight
+ * serving loops, harnesses that forbid allocation): no hipMalloc, hipFree or
+ * allocator callback is called.  The kernel writes into a file-scope device
+ * array of the library (5 doubles for each of at most 8192 live replicas,
+ * 320 KiB, held on every device the library runs on until the process ends)
+ * and the results are copied to the host; out holds 5 doubles per replica
+ * slot (islf_num_replicas), NaN for retired slots.  The array is shared by
+ * every call on one device: calls on contexts of the same device that
+ * overlap in time (other threads) race, so serialise them.  Synchronises.
+ * Errors: EINVAL (NULL), ERANGE (more than 8192 live replicas, or a replica
+ * lacks a requested record), ESTATE (replica tables not current after
+ * islf_set_tile, or a failed replica), EDEVICE. */
+islf_status islf_means_noalloc(islf_ctx *ctx, uint64_t first, uint32_t count, double *out);
+
 /* The same means for one replica: out[0..4] = mean {E, B, M, M1, Mn} over
  * its records first .. first+count-1.  Host out; synchronises. */
 islf_status islf_replica_means(islf_ctx *ctx, int32_t rep, uint64_t first, uint32_t count, double *out);

@@ -41,6 +41,7 @@ hipError_t launch_means(const RepDesc *descs, const int *reps, int n, uint64_t f
                         double *out, hipStream_t s);
 hipError_t launch_integrate(const double *h, const double *m1, const double *mn, int n, double c1, double cn,
                             double norm, double *out, hipStream_t s);
+hipError_t noalloc_scratch(double **out);
 }  // namespace islf
 
 using namespace islf;
@@ -221,6 +222,7 @@ struct islf_ctx {
     int grid_override = 0;     // workgroups per batched / plain launch (0: sweep_slots)
     int persistent_grid = 0;   // workgroups of the persistent kernel's cooperative launch
     int persistent_bound = 0;  // co-residency bound computed for it on this device
+    double *noalloc_scratch = nullptr;   // this device's copy of the means scratch array
 
     std::vector<Replica> reps;
     int slot_capacity = 0;
@@ -887,6 +889,10 @@ extern "C" islf_status islf_create_with_allocator(const islf_replica_desc *reps,
     // expired
     const int per_cu_p = per_cu > 1 ? per_cu - 1 : 1;
     c->persistent_grid = std::min(c->num_cu * per_cu_p, c->persistent_bound);
+    if (noalloc_scratch(&c->noalloc_scratch) != hipSuccess) {
+        delete c;
+        return fail(ISLF_EDEVICE, "cannot look up the means scratch array on device %d", dev);
+    }
     c->d_sync = (GridSync *)dev_alloc(c, sizeof(GridSync));
     c->d_scratch = (unsigned long long *)dev_alloc(c, 64 * sizeof(unsigned long long));
     if (!c->d_sync || !c->d_scratch) {
@@ -1340,6 +1346,52 @@ extern "C" islf_status islf_energy(const islf_replica_desc *desc, const islf_obs
 
 // Host FP64 cumulative trapezoid (Eq. 9 / Eq. 22 over the field, Eq. 19 over
 // beta), left to right.
+// The means of islf_means with the kernel's output in the device's scratch
+// array instead of a staging allocation; the per-replica results are copied
+// to the front of out and moved to their slots from the back (slot ids of
+// live replicas are ascending and never below their rank, so no result is
+// overwritten before it is moved).
+extern "C" islf_status islf_means_noalloc(islf_ctx *ctx, uint64_t first, uint32_t count, double *out)
+{
+    if (!ctx || !out) return fail(ISLF_EINVAL, "NULL argument");
+    if (ctx->dirty)
+        return fail(ISLF_ESTATE, "replica tables are not current (after islf_set_tile, sweep or call islf_means once)");
+    const int n = (int)ctx->reps.size();
+    const int nl = (int)ctx->live.size();
+    if (nl > kNoAllocMaxReps)
+        return fail(ISLF_ERANGE, "%d live replicas exceed the %d the allocation-free means serve per call", nl,
+                    kNoAllocMaxReps);
+    islf_status st;
+    for (int r : ctx->live) {
+        st = check_records(ctx, r, first, count);
+        if (st != ISLF_OK) return st;
+    }
+    st = check_device_error(ctx);
+    if (st != ISLF_OK) return st;
+    st = check_none_failed(ctx);
+    if (st != ISLF_OK) return st;
+    if (nl > 0) {
+        HIP_TRY(launch_means(ctx->d_desc, ctx->d_live, nl, first, count, ctx->noalloc_scratch, ctx->stream));
+        HIP_TRY(hipMemcpyAsync(out, ctx->noalloc_scratch, sizeof(double) * 5 * nl, hipMemcpyDeviceToHost,
+                               ctx->stream));
+        HIP_TRY(hipStreamSynchronize(ctx->stream));
+    }
+    for (int i = nl - 1; i >= 0; --i) {
+        const int r = ctx->live[i];
+        if (r != i)
+            for (int k = 0; k < 5; ++k) out[5 * r + k] = out[5 * i + k];
+    }
+    int li = 0;
+    for (int r = 0; r < n; ++r) {
+        if (li < nl && ctx->live[li] == r) {
+            ++li;
+            continue;
+        }
+        for (int k = 0; k < 5; ++k) out[5 * r + k] = NAN;
+    }
+    return ISLF_OK;
+}
+
 extern "C" islf_status islf_integrate(const double *h, const double *mean_M1, const double *mean_Mn, int32_t n,
                                       double c1, double cn, double norm, double *cumulative_out)
 {

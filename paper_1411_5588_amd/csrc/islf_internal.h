@@ -16,6 +16,7 @@ constexpr int kThrPerClass = 16;     // index u*8 + cnt, cnt in 0..6
 constexpr int kThrEntries = kClasses * kThrPerClass;
 constexpr int kPadEntry = kThrEntries - 1;   // class 3, u = 1, cnt = 7: never a real site
 constexpr int kMaxMarch = 256;       // x planes one thread may march through per entry
+constexpr int kNoAllocMaxReps = 8192;   // live replicas islf_means_noalloc serves per call
 
 // One item of work for one replica.  j counts 8-byte chunks (int8 format) or
 // 32-bit words of one sublattice row (bit-packed).

@@ -17,6 +17,8 @@
 //    counts are bit-sliced with full adders.
 // Both formats draw the same Philox word for the same site, so they give the
 // same Markov chain.
+#include <mutex>
+
 #include "islf_internal.h"
 
 #pragma clang fp contract(off)
@@ -1436,6 +1438,38 @@ __global__ void k_integrate(const double *__restrict__ h, const double *__restri
         out[r] = acc;
         g_prev = g;
     }
+}
+
+// ---------------------------------------------------------------------------
+// Scratch of the allocation-free means (islf_means_noalloc): a file-scope
+// device array of kNoAllocMaxReps x 5 doubles (320 KiB) that the means kernel
+// writes in place of a staging buffer.  Each device holds its own copy for
+// the life of the process; host code reaches it only through the address
+// hipGetSymbolAddress returns on that device, looked up once per device.
+// ---------------------------------------------------------------------------
+static __device__ __align__(256) double scratch[5 * kNoAllocMaxReps];
+
+constexpr int kMaxDevices = 64;
+static std::mutex g_scratch_mu;
+static void *g_scratch_addr[kMaxDevices];
+
+// The current device's address of `scratch` (looked up on its first use on
+// that device, with that device current).
+hipError_t noalloc_scratch(double **out)
+{
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return e;
+    if (dev < 0 || dev >= kMaxDevices) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_addr[dev]) {
+        void *p = nullptr;
+        e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return e;
+        g_scratch_addr[dev] = p;
+    }
+    *out = (double *)g_scratch_addr[dev];
+    return hipSuccess;
 }
 
 // ---------------------------------------------------------------------------

@@ -101,6 +101,7 @@ def lib():
             "islf_record_energy": [vp, i32, u64, u32, vp],
             "islf_energy": [P(ReplicaDesc), vp, sz, vp],
             "islf_means": [vp, u64, u32, vp],
+            "islf_means_noalloc": [vp, u64, u32, vp],
             "islf_integrate": [vp, vp, vp, i32, dbl, dbl, dbl, vp],
             "islf_integrate_device": [vp, vp, vp, i32, dbl, dbl, dbl, vp, vp],
             "islf_footprint_bytes": [P(ReplicaDesc), i32, u32, P(u64)],
@@ -151,7 +152,10 @@ class _TorchAllocator:
         self.device = device
         self.stream = stream
 
+        self.calls = 0   # allocation requests the library has made through this hook
+
         def _alloc(nbytes, user):
+            self.calls += 1
             try:
                 return int(torch.cuda.caching_allocator_alloc(int(nbytes), device=self.device,
                                                               stream=self.stream))
@@ -271,6 +275,14 @@ class Context:
         _check(lib().islf_num_replicas(self._h, C.byref(n)))
         out = np.zeros((n.value, 5), dtype=np.float64)
         _check(lib().islf_means(self._h, first, count, out.ctypes.data_as(C.c_void_p)))
+        return out
+
+    def means_noalloc(self, first, count) -> np.ndarray:
+        """means() through the allocation-free entry point (islf_means_noalloc)."""
+        n = C.c_int32()
+        _check(lib().islf_num_replicas(self._h, C.byref(n)))
+        out = np.zeros((n.value, 5), dtype=np.float64)
+        _check(lib().islf_means_noalloc(self._h, first, count, out.ctypes.data_as(C.c_void_p)))
         return out
 
     def replica_means(self, rep, first, count) -> np.ndarray:
