@@ -101,12 +101,19 @@ static int num_tiles_of(int fmt) { return fmt == ISLF_SPIN_INT8 ? kNumI8Tiles : 
 
 static long ceil_div(long a, long b) { return (a + b - 1) / b; }
 
+// Columns of one sublattice row a thread takes: 8-byte columns (8 sites,
+// int8) or 32-bit words (32 sites, bit-packed).
+static long columns_of(const islf_replica_desc &d, int fmt)
+{
+    return fmt == ISLF_SPIN_INT8 ? (d.Lz + 15) / 16 : (d.Lz + 63) / 64;
+}
+
 struct I8Shape {
     int tj, ty, mx;
 };
 static I8Shape i8_shape(const islf_replica_desc &d, int tile, int fmt = ISLF_SPIN_INT8)
 {
-    const long C = fmt == ISLF_SPIN_INT8 ? (d.Lz + 7) / 8 : (d.Lz + 63) / 64;
+    const long C = columns_of(d, fmt);
     const I8Tile &t = fmt == ISLF_SPIN_INT8 ? kI8Tiles[tile] : kBpTilesM[tile];
     I8Shape s;
     s.mx = std::min(t.mx, d.Lx);
@@ -126,7 +133,7 @@ static double tile_efficiency(const islf_replica_desc &d, int fmt, int tile)
 {
     const double ny = d.Ly - 3;
     if (ny <= 0) return 1.0;
-    const long C = fmt == ISLF_SPIN_INT8 ? (d.Lz + 7) / 8 : (d.Lz + 63) / 64;
+    const long C = columns_of(d, fmt);
     const I8Shape s = i8_shape(d, tile, fmt);
     const double per_plane = s.tj == 0 ? (double)ceil_div((long)ny * C, kBlock)
                                        : (double)ceil_div((long)ny, s.ty) * ceil_div(C, s.tj);
@@ -162,7 +169,7 @@ struct SlabShape {
 // fewest entries
 static SlabShape slab_shape(const islf_replica_desc &d, int fmt)
 {
-    const long J = fmt == ISLF_SPIN_INT8 ? (d.Lz + 7) / 8 : (d.Lz + 63) / 64;
+    const long J = columns_of(d, fmt);
     const long P = (d.Lx + 1) / 2;
     const long cap = kBlock / 2;
     SlabShape best{1, 1};
@@ -304,7 +311,7 @@ static islf_status validate(const islf_replica_desc *d)
     const unsigned long long chunks = rows * (unsigned long long)((d->Lz + 7) / 8);
     if (chunks * 2ull > (1ull << 32))
         return fail(ISLF_ERANGE, "lattice %dx%dx%d exceeds the 32-bit Philox group counter", d->Lx, d->Ly, d->Lz);
-    if (chunks * 8ull >= (1ull << 32))
+    if (rows * 16ull * (unsigned long long)((d->Lz + 15) / 16) >= (1ull << 32))
         return fail(ISLF_ERANGE, "lattice %dx%dx%d exceeds 4 GiB of int8 spins", d->Lx, d->Ly, d->Lz);
     return ISLF_OK;
 }
@@ -312,7 +319,7 @@ static islf_status validate(const islf_replica_desc *d)
 static size_t spin_bytes(const islf_replica_desc *d, int fmt)
 {
     const size_t rows = (size_t)d->Lx * d->Ly;
-    if (fmt == ISLF_SPIN_INT8) return rows * 8 * (size_t)((d->Lz + 7) / 8);
+    if (fmt == ISLF_SPIN_INT8) return rows * 16 * (size_t)((d->Lz + 15) / 16);
     return rows * 2 * 4 * (size_t)((d->Lz + 63) / 64);
 }
 
@@ -364,7 +371,7 @@ static void build_work(Replica &R, int rep_id, int fmt)
     const islf_replica_desc &d = R.desc;
     R.main.clear();
     R.slab.clear();
-    const int J = fmt == ISLF_SPIN_INT8 ? (d.Lz + 7) / 8 : (d.Lz + 63) / 64;
+    const int J = (int)columns_of(d, fmt);
     const I8Shape s = i8_shape(d, R.tile, fmt);
     const int cols = std::max(0, d.Ly - 3) * J;   // main columns of a plane (rows 2 .. Ly-2)
     for (int x0 = 0; x0 < d.Lx; x0 += s.mx) {
@@ -401,7 +408,9 @@ static void fill_desc(Replica &R, int fmt, uint32_t cap)
     build_tables(&d, D);
     D.Lx = d.Lx; D.Ly = d.Ly; D.Lz = d.Lz;
     D.C = (d.Lz + 7) / 8;
-    D.Lzp = 8 * D.C;
+    D.K = (d.Lz + 15) / 16;
+    D.Hp = 8 * D.K;
+    D.RB = 2 * D.Hp;
     D.Wq = (d.Lz + 63) / 64;
     D.seam_reflect = d.ybc == ISLF_YBC_GAPBC;
     D.seam_invert = d.ybc != ISLF_YBC_PBC;
@@ -1731,7 +1740,7 @@ extern "C" islf_status islf_autotune(islf_ctx *ctx, uint32_t sweeps)
 // 32-bit words per (x, y) row of the spin array
 static long profile_row_words(const Replica &R)
 {
-    return R.d.fmt == ISLF_SPIN_INT8 ? R.d.Lzp / 4 : 2l * R.d.Wq;
+    return R.d.fmt == ISLF_SPIN_INT8 ? R.d.RB / 4 : 2l * R.d.Wq;
 }
 
 extern "C" islf_status islf_layer_profile(islf_ctx *ctx, int32_t rep, int32_t *dev_out)

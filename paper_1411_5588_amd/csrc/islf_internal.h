@@ -18,8 +18,9 @@ constexpr int kPadEntry = kThrEntries - 1;   // class 3, u = 1, cnt = 7: never a
 constexpr int kMaxMarch = 256;       // x planes one thread may march through per entry
 constexpr int kNoAllocMaxReps = 8192;   // live replicas islf_means_noalloc serves per call
 
-// One item of work for one replica.  j counts 8-byte chunks (int8 format) or
-// 32-bit words of one sublattice row (bit-packed).
+// One item of work for one replica.  j counts 8-byte columns of one
+// sublattice row (int8 format: 8 sites) or 32-bit words of one sublattice
+// row (bit-packed: 32 sites).
 // Main tile (kind 0, rows 2 .. Ly-2): a box of rows/columns starting at
 // (x0, y0, j0) whose extent is the replica's tile shape, or (linear tile
 // shape, i8_tj = 0) the columns [y0, j0) of a plane's main rows in row-major
@@ -40,7 +41,7 @@ enum { FLAG_PREV = 1, FLAG_FOLD = 2 };   // A: do the previous sweep's phase 3; 
 
 // Read-only description of a replica as the kernels see it.
 struct RepDesc {
-    uint8_t *spins;        // int8 format: byte 1 = up, 0 = down; rows of Lzp bytes
+    uint8_t *spins;        // int8 format: byte 1 = up, 0 = down; rows of RB = 2*Hp bytes (even z, odd z)
                            // bit-packed: rows of 2*Wq uint32 words (even z, odd z)
     islf_obs *rec;         // ring of cap per-sweep records
     long long *acc;        // 2 x kAccSlots x 4 partial sums (double-buffered by t & 1)
@@ -49,8 +50,10 @@ struct RepDesc {
     int32_t dpack[kThrEntries];    // change of (B, M) on a flip: dB + 65536 * dM
     uint64_t never_mask;           // bit i set when thr[i] == 0 (no draw can accept)
     int32_t Lx, Ly, Lz;
-    int32_t C;             // chunks of 8 sites per row, ceil(Lz/8)
-    int32_t Lzp;           // int8 row stride in bytes, 8*C
+    int32_t C;             // Philox groups of 8 consecutive z per row, ceil(Lz/8)
+    int32_t K;             // int8 8-byte columns per sublattice row, ceil(Lz/16)
+    int32_t Hp;            // int8 bytes per sublattice row, 8*K
+    int32_t RB;            // int8 row stride in bytes, 2*Hp
     int32_t Wq;            // bit-packed words per sublattice row, ceil(Lz/64)
     int32_t seam_reflect;  // 1: the y seam maps x -> Lx-1-x
     int32_t seam_invert;   // 1: the y seam carries eps = -1

@@ -6,11 +6,14 @@
 //
 // The path is integer stencil work plus Philox4x32-10: no matrix cores.  Two
 // spin formats:
-//  * int8: one byte per site, 1 = up, 0 = down, rows of Lzp = 8*ceil(Lz/8)
-//    bytes, z fastest, row index x*Ly + y.  A thread owns one 8-byte chunk of
-//    a row: the 4 sites of the current phase in it share one Philox call, and
-//    the neighbour counts of all 8 bytes are formed with plain 64-bit adds
-//    (each byte holds 0/1, sums stay below 8, so no carry crosses a byte).
+//  * int8: one byte per site, 1 = up, 0 = down; each row (x, y) is split
+//    into its even-z sublattice (z = 2i at byte i) and its odd-z sublattice
+//    (z = 2i+1 at byte Hp + i), Hp = 8*ceil(Lz/16), row index x*Ly + y,
+//    padding bytes 0.  The sites of one phase in a row are one sublattice,
+//    so a thread owns an 8-byte column of it: 8 sites of the phase, two
+//    Philox calls, one 8-byte store of its own sites only; neighbour counts
+//    of all 8 bytes are formed with word-wide adds (each byte holds 0/1, sums
+//    stay below 8, so no carry crosses a byte).
 //  * bit-packed: one bit per site, each row split into its even-z and odd-z
 //    sublattices of Lz/2 bits.  A thread owns one 32-bit word of one
 //    sublattice row (32 sites of the same phase, 8 Philox calls); neighbour
@@ -137,8 +140,8 @@ __device__ __forceinline__ void load_tables(const RepDesc &d, Tables *t)
 struct RepView {
     uint8_t *spins;
     long long *acc;
-    int Lx, Ly, Lz, C, Wq;
-    uint32_t Lzp;           // int8 row stride in bytes
+    int Lx, Ly, Lz, C, Wq, K;
+    uint32_t Hp, RB;        // int8 sublattice row and row bytes
     int seam_reflect, seam_invert;
     uint32_t key0, key1, replica, t;
     int tj, ty, mx;          // marching tile (tj = 0: linear tiles)
@@ -153,8 +156,9 @@ __device__ __forceinline__ RepView load_view(const RepDesc *__restrict__ descs, 
     RepView v;
     v.spins = d.spins;
     v.acc = d.acc;
-    v.Lx = d.Lx; v.Ly = d.Ly; v.Lz = d.Lz; v.C = d.C; v.Wq = d.Wq;
-    v.Lzp = (uint32_t)d.Lzp;
+    v.Lx = d.Lx; v.Ly = d.Ly; v.Lz = d.Lz; v.C = d.C; v.Wq = d.Wq; v.K = d.K;
+    v.Hp = (uint32_t)d.Hp;
+    v.RB = (uint32_t)d.RB;
     v.seam_reflect = d.seam_reflect;
     v.seam_invert = d.seam_invert;
     v.key0 = d.key0; v.key1 = d.key1; v.replica = d.replica;
@@ -222,77 +226,89 @@ __device__ __forceinline__ void st32(uint8_t *base, uint32_t off, uint32_t v)
     else *p = v;
 }
 
-template <bool COH>
-__device__ __forceinline__ void i8_update_chunk(const RepView &v, int x, int y, int j, int parity,
-                                                const uint64_t *sthr, Acc &a)
+// Bytes [0, nv) of an 8-byte column set.
+__device__ __forceinline__ uint64_t byte_mask(int nv)
 {
-    const int Lx = v.Lx, Ly = v.Ly, C = v.C, Lz = v.Lz;
-    const uint32_t Lzp = v.Lzp;
-    uint8_t *sp = v.spins;
-    const uint32_t row = (uint32_t)x * (uint32_t)Ly + (uint32_t)y;
-    const uint32_t rowoff = row * Lzp;
-    const uint32_t jo = 8u * (uint32_t)j;
-    const uint32_t off = rowoff + jo;
-    const int q = (parity + x + y) & 1;
-    const bool last = (j == C - 1);
-    const int r = last ? (Lz - 8 * (C - 1)) : 8;
+    return nv >= 8 ? ~0ull : ((1ull << (8 * nv)) - 1ull);
+}
 
-    // neighbour rows; a missing x neighbour (free surface) reads the own
-    // chunk and is masked out, a seam neighbour is inverted when eps = -1
+// One 8-byte column k of the phase's sublattice of row (x, y): 8 sites
+// z = 2i + q, i = 8k .. 8k+7 (the last column of a row may hold fewer).
+// Philox call c (counter g + 2c) draws for sites i = 8k + 4c .. 8k + 4c + 3
+// (their 8-site group is i >> 2 = 2k + c, word i & 3).  Used by the
+// seam-slab stages: any row, the y seam, 64-bit thresholds of any class.
+template <bool COH>
+__device__ __forceinline__ void i8_update_col(const RepView &v, int x, int y, int k, int parity,
+                                              const uint64_t *sthr, Acc &a)
+{
+    const int Lx = v.Lx, Ly = v.Ly, K = v.K;
+    const int Lzh = v.Lz >> 1;
+    const uint32_t RB = v.RB, Hp = v.Hp;
+    uint8_t *sp = v.spins;
+    const int q = (parity + x + y) & 1;
+    const uint32_t row = (uint32_t)x * (uint32_t)Ly + (uint32_t)y;
+    const uint32_t rowoff = row * RB;
+    const uint32_t co = 8u * (uint32_t)k;
+    const uint32_t qo = (uint32_t)q * Hp + co;            // column offset inside a row
+    const uint32_t own = rowoff + qo;
+    const uint32_t oth = rowoff + (uint32_t)(q ^ 1) * Hp + co;
+    const bool last = (k == K - 1);
+    const int nv = last ? Lzh - 8 * (K - 1) : 8;
+
+    // z neighbours from the other sublattice O of the row: q = 0 (z = 2i):
+    // z+1 is odd index i, z-1 odd index i-1; q = 1 (z = 2i+1): z-1 is even
+    // index i, z+1 even index i+1 (wrapping at the row's ends)
+    const uint64_t O = ld64<COH>(sp, oth);
+    uint64_t Z;
+    if (q == 0) {
+        const uint32_t eo = k > 0 ? oth - 1u : rowoff + Hp + (uint32_t)(Lzh - 1);
+        Z = (O << 8) | ld8<COH>(sp, eo);
+    } else {
+        const uint32_t eo = last ? rowoff : oth + 8u;
+        Z = (O >> 8) | (ld8<COH>(sp, eo) << (8 * (nv - 1)));
+    }
+    // y neighbours (the seam remaps x and inverts when eps = -1; a padding
+    // byte may turn to 1 there, it is never a site) and x neighbours (a free
+    // surface contributes 0)
     const uint32_t xs = v.seam_reflect ? (uint32_t)(Lx - 1 - x) : (uint32_t)x;
     const uint64_t seam_mask = v.seam_invert ? kOnes8 : 0ull;
     const bool ytop = (y == Ly - 1), ybot = (y == 0);
     const uint32_t rp = ytop ? xs * (uint32_t)Ly : row + 1u;
     const uint32_t rm = ybot ? xs * (uint32_t)Ly + (uint32_t)(Ly - 1) : row - 1u;
-    const uint64_t inv_p = ytop ? seam_mask : 0ull;
-    const uint64_t inv_m = ybot ? seam_mask : 0ull;
-    const uint32_t xstride = (uint32_t)Ly * Lzp;
-    const bool has_xm = x > 0, has_xp = x < Lx - 1;
-    const uint32_t oxm = has_xm ? off - xstride : off;
-    const uint32_t oxp = has_xp ? off + xstride : off;
-    const uint32_t oprev = (j > 0) ? off - 1u : rowoff + (uint32_t)(Lz - 1);
-    const uint32_t onext = last ? rowoff : off + 8u;
+    const uint64_t Yp = ld64<COH>(sp, rp * RB + qo) ^ (ytop ? seam_mask : 0ull);
+    const uint64_t Ym = ld64<COH>(sp, rm * RB + qo) ^ (ybot ? seam_mask : 0ull);
+    const uint32_t xstride = (uint32_t)Ly * RB;
+    const uint64_t Xm = x > 0 ? ld64<COH>(sp, own - xstride) : 0ull;
+    const uint64_t Xp = x < Lx - 1 ? ld64<COH>(sp, own + xstride) : 0ull;
+    const uint64_t S = ld64<COH>(sp, own);
 
-    const uint64_t W = ld64<COH>(sp, off);
-    const uint64_t Yp = ld64<COH>(sp, rp * Lzp + jo);
-    const uint64_t Ym = ld64<COH>(sp, rm * Lzp + jo);
-    const uint64_t Xm = ld64<COH>(sp, oxm);
-    const uint64_t Xp = ld64<COH>(sp, oxp);
-    const uint64_t prev = ld8<COH>(sp, oprev);
-    const uint64_t next = ld8<COH>(sp, onext);
-
-    uint64_t cnt = ((W << 8) | prev) + ((W >> 8) | (next << (8 * (r - 1))));
-    cnt += (Yp ^ inv_p) + (Ym ^ inv_m);
-    cnt += (has_xm ? Xm : 0ull) + (has_xp ? Xp : 0ull);
-
+    const uint64_t cnt = ((O + Z) + (Yp + Ym)) + (Xm + Xp);
     const int cls = (x == 0 ? 1 : 0) + (x == Lx - 1 ? 2 : 0);
-    const int k = 6 - (x == 0) - (x == Lx - 1);
-    const uint64_t idxw = cnt + (W << 3);   // per byte: 8*u + count
+    const int kn = 6 - (x == 0) - (x == Lx - 1);
+    const uint64_t idxw = cnt + (S << 3);   // per byte: 8*u + count
 
-    const uint32_t g = ((row * (uint32_t)C + (uint32_t)j) << 1) | (uint32_t)q;
-    uint32_t rnd[4];
-    philox10(g, v.t, v.replica, 0u, v.key0, v.key1, rnd);
+    const uint32_t g = ((row * (uint32_t)v.C + 2u * (uint32_t)k) << 1) | (uint32_t)q;
+    uint32_t r0[4], r1[4];
+    philox10<0u>(g, v.t, v.replica, 0u, v.key0, v.key1, r0);
+    philox10<2u>(g, v.t, v.replica, 0u, v.key0, v.key1, r1);
 
     const uint64_t *tc = sthr + cls * kThrPerClass;
     uint64_t flip = 0;
 #pragma unroll
-    for (int l = 0; l < 4; ++l) {
-        const int pos = q + 2 * l;
-        const uint32_t e = (uint32_t)(idxw >> (8 * pos)) & 0xFFu;
-        const uint64_t thr = tc[e];
-        flip |= (uint64_t)((uint64_t)rnd[l] < thr) << (8 * pos);
+    for (int b = 0; b < 8; ++b) {
+        const uint32_t e = (uint32_t)(idxw >> (8 * b)) & 0xFFu;
+        const uint32_t u = b < 4 ? r0[b] : r1[b - 4];
+        flip |= (uint64_t)((uint64_t)u < tc[e & 0xF]) << (8 * b);
     }
-    // sites past the end of a short last chunk are padding
-    const uint64_t valid = (r == 8) ? ~0ull : ((1ull << (8 * r)) - 1ull);
-    flip &= valid;
-    st64<COH>(sp, off, W ^ flip);
+    flip &= byte_mask(nv);
+    st64<COH>(sp, own, S ^ flip);
 
     // dB = -2 sum_f s n with s = 2u-1, n = 2 cnt - k;  dM = sum_f (2 - 4u)
-    const uint64_t fu = flip & W;
+    const uint64_t fu = flip & S;
     const int nf = __popcll(flip), nfu = __popcll(fu);
     const uint64_t fm = (flip << 8) - flip, fum = (fu << 8) - fu;
     const int Sf = (int)bytesum64(cnt & fm), Sfu = (int)bytesum64(cnt & fum);
-    a.dB += -2 * (4 * Sfu - 2 * k * nfu - 2 * Sf + k * nf);
+    a.dB += -2 * (4 * Sfu - 2 * kn * nfu - 2 * Sf + kn * nf);
     const int dm = 2 * nf - 4 * nfu;
     a.dM += dm;
     if (x == 0) a.dM1 += dm;
@@ -395,43 +411,6 @@ __device__ __forceinline__ void bp_update_word(const RepView &v, int x, int y, i
 // ---------------------------------------------------------------------------
 // int8 format, main tiles.
 // ---------------------------------------------------------------------------
-struct MarchLane {
-    uint32_t oc, oym, oyp, oprev, onext;   // offsets inside the current x plane
-    uint64_t valid, padidx;                // short last chunk: real bytes / padding index
-    int r;
-};
-
-// Neighbour data of one x step, loaded one step ahead of its use.
-struct StepIn {
-    uint64_t Wn, Yp, Ym;
-    uint32_t pb, nb;
-};
-
-// xo: byte offset of plane x in the replica's spin array
-template <bool COH>
-__device__ __forceinline__ StepIn load_step(const RepView &v, const MarchLane &L, uint32_t xo, int x,
-                                            uint32_t xstride)
-{
-    StepIn in;
-    in.Wn = (x + 1 < v.Lx) ? ld64<COH>(v.spins, xo + xstride + L.oc) : 0ull;
-    in.Yp = ld64<COH>(v.spins, xo + L.oyp);
-    in.Ym = ld64<COH>(v.spins, xo + L.oym);
-    in.pb = (uint32_t)ld8<COH>(v.spins, xo + L.oprev);
-    in.nb = (uint32_t)ld8<COH>(v.spins, xo + L.onext);
-    return in;
-}
-
-// int8 format, main tiles (rows 2 .. Ly-2): a thread owns one chunk column
-// (x0..x1-1, y, j) of its tile and marches through the x planes.  The chunk of
-// plane x-1 (read before its update: only its other-parity bytes are used,
-// and those are not written in this phase) and of plane x+1 stay in
-// registers; the y neighbours, the z-edge bytes and the next plane are loaded
-// one step ahead (none of them is written by this thread's current step, and
-// the bytes used are not written in this phase at all).  The per-byte table
-// index 4*(cnt + 8u + 16*class) is formed with word-wide adds on the two
-// 32-bit halves of the chunk; a shift by 8q moves the four sites of the phase
-// to bytes 0 and 2 of each half.  A flip adds its packed (dB, dM) change to a
-// register sum.
 // The column a thread of a main tile marches: row y (2 .. Ly-2) and column j
 // (< ncol chunks or words), or false when the thread has none.  A box tile
 // is v.ty rows x v.tj columns from (en.y0, en.j0); a linear tile (v.tj = 0)
@@ -451,112 +430,142 @@ __device__ __forceinline__ bool main_column(const RepView &v, const Entry &en, i
     return lin < en.j0;
 }
 
+// Words of one int8 march step, loaded one step ahead of their use.
+struct I8Step {
+    uint64_t S, yp, ym, xp;   // own column, rows y+1 / y-1 and plane x+1 at the same column
+    uint32_t e;               // the z-edge byte of the other sublattice
+};
+
+template <bool COH>
+__device__ __forceinline__ I8Step i8_load_step(const uint8_t *sp, uint32_t own, uint32_t edge, uint32_t RB,
+                                               uint32_t XB, bool has_xp)
+{
+    I8Step n;
+    n.S = ld64<COH>(sp, own);
+    n.e = (uint32_t)ld8<COH>(sp, edge);
+    n.yp = ld64<COH>(sp, own + RB);
+    n.ym = ld64<COH>(sp, own - RB);
+    n.xp = has_xp ? ld64<COH>(sp, own + XB) : 0ull;
+    return n;
+}
+
+// int8 format, main tiles (rows 2 .. Ly-2): a thread owns column k of its
+// row's sublattices and marches through the x planes; at plane x it updates
+// the 8 sites of sublattice q = (parity + x + y) & 1 in the column.  Of the
+// words a step reads, the other sublattice of plane x (O: the z neighbours)
+// and the same sublattice of plane x+1 (the x+1 neighbours) are the next
+// step's x-1 and other-sublattice words, so they stay in registers; the own
+// column, the z-edge byte, rows y+-1 and plane x+2 are loaded one step
+// ahead.  None of these bytes is written in this phase.  The per-byte table
+// index 8*(8u + cnt) is the byte offset of the site's (thr - 1, packed flip
+// change) entry; the plane's class (x = 0, Lx-1) moves the table base.  A
+// flip adds its packed (dB, dM) change to a register sum.
 template <bool NEVER, bool RAGGED, bool COH>
 __device__ __forceinline__ void i8_march(const RepView &v, const Entry &en, int k_lo, int k_hi, int parity,
                                          const Tables *tb, Acc &a)
 {
-    int y, j;
-    if (!main_column(v, en, v.C, y, j)) return;
-    const int Lx = v.Lx, Ly = v.Ly, C = v.C, Lz = v.Lz;
-    const uint32_t Lzp = v.Lzp;
+    int y, k;
+    if (!main_column(v, en, v.K, y, k)) return;
+    const int Lx = v.Lx, Ly = v.Ly, K = v.K;
+    const int Lzh = v.Lz >> 1;
+    const uint32_t RB = v.RB, Hp = v.Hp;
+    const uint32_t XB = (uint32_t)Ly * RB;   // bytes of one x plane
+    const uint32_t co = 8u * (uint32_t)k;
+    const bool last = (k == K - 1);
+    const int nv = RAGGED && last ? Lzh - 8 * (K - 1) : 8;
+    // the z-edge byte: own q = 0 needs odd byte 8k-1 (Lzh-1 for k = 0) at
+    // bit 0; own q = 1 needs even byte 8k+8 (byte 0 for the last column) at
+    // byte nv-1
+    const uint32_t e0 = Hp + (k > 0 ? co - 1u : (uint32_t)(Lzh - 1));
+    const uint32_t e1 = last ? 0u : co + 8u;
+    const uint32_t esh = RAGGED ? 8u * (uint32_t)(nv - 1) : 24u;   // in the high word unless ragged
     const int x0 = en.x0 + k_lo;
     const int x1 = min(en.x0 + k_hi, Lx);
-    const uint32_t xstride = (uint32_t)Ly * Lzp;
-    const uint32_t jo = 8u * (uint32_t)j;
-    const bool last = (j == C - 1);
-
-    MarchLane L;
-    L.r = last ? (Lz - 8 * (C - 1)) : 8;
-    const uint32_t yrow = (uint32_t)y * Lzp;
-    L.oc = yrow + jo;
-    L.oym = L.oc - Lzp;
-    L.oyp = L.oc + Lzp;
-    L.oprev = (j > 0) ? L.oc - 1u : yrow + (uint32_t)(Lz - 1);
-    L.onext = last ? yrow : L.oc + 8u;
-    L.valid = (L.r == 8) ? ~0ull : ((1ull << (8 * L.r)) - 1ull);
-    L.padidx = ~L.valid & (0x0101010101010101ull * (uint64_t)(4 * kPadEntry));
-
-    uint32_t xo = (uint32_t)x0 * xstride;   // byte offset of plane x (a replica is below 4 GiB)
-    const uint32_t gstep = 2u * (uint32_t)Ly * (uint32_t)C;
     int q = (parity + x0 + y) & 1;
-    uint32_t g = ((((uint32_t)x0 * (uint32_t)Ly + (uint32_t)y) * (uint32_t)C + (uint32_t)j) << 1) | (uint32_t)q;
+    uint32_t rw = ((uint32_t)x0 * (uint32_t)Ly + (uint32_t)y) * RB;   // byte offset of row (x, y)
+    const uint32_t gstep = 2u * (uint32_t)Ly * (uint32_t)v.C;
+    uint32_t g = ((((uint32_t)x0 * (uint32_t)Ly + (uint32_t)y) * (uint32_t)v.C + 2u * (uint32_t)k) << 1) |
+                 (uint32_t)q;
 
-    uint64_t Wc = ld64<COH>(v.spins, xo + L.oc);
-    uint64_t Wm = (x0 > 0) ? ld64<COH>(v.spins, xo - xstride + L.oc) : 0ull;
-    StepIn cur = load_step<COH>(v, L, xo, x0, xstride);
+    auto own_of = [&](uint32_t r, int qq) { return r + (qq ? Hp : 0u) + co; };
+    auto edge_of = [&](uint32_t r, int qq) { return r + (qq ? e1 : e0); };
+    uint64_t O = ld64<COH>(v.spins, own_of(rw, q ^ 1));
+    uint64_t xm = x0 > 0 ? ld64<COH>(v.spins, own_of(rw, q) - XB) : 0ull;
+    I8Step cur = i8_load_step<COH>(v.spins, own_of(rw, q), edge_of(rw, q), RB, XB, x0 < Lx - 1);
     // the surface planes x = 0 and Lx-1 can only be the first and last of
     // the march: their sums are the first and last steps' (no per-step test)
     int dsum = 0, dfirst = 0, dlast = 0;
     bool first = true;
     for (int x = x0; x < x1; ++x) {
-        // next step's neighbours first: independent of this step's result
-        StepIn nxt;
+        const uint32_t own = own_of(rw, q);
+        I8Step nxt;
         const bool more = x + 1 < x1;
-        if (more) nxt = load_step<COH>(v, L, xo + xstride, x + 1, xstride);
+        if (more) nxt = i8_load_step<COH>(v.spins, own_of(rw + XB, q ^ 1), edge_of(rw + XB, q ^ 1), RB, XB, x + 2 < Lx);
         // bytes hold 0/1 and their sums stay below 8, so no carry crosses a
-        // byte: each 32-bit half of the chunk is summed on its own
-        const uint32_t wl = (uint32_t)Wc, wh = (uint32_t)(Wc >> 32);
-        const uint32_t zml = (wl << 8) | cur.pb;
-        const uint32_t zmh = __builtin_amdgcn_alignbit(wh, wl, 24);
-        uint32_t zpl = __builtin_amdgcn_alignbit(wh, wl, 8);
-        uint32_t zph = wh >> 8;
-        if (RAGGED) {
-            const uint64_t nbw = (uint64_t)cur.nb << (8 * (L.r - 1));
-            zpl |= (uint32_t)nbw;
-            zph |= (uint32_t)(nbw >> 32);
+        // byte: each 32-bit half of the column is summed on its own
+        const uint32_t ol = (uint32_t)O, oh = (uint32_t)(O >> 32);
+        uint32_t zl, zh;
+        if (q) {
+            // z+1: the other sublattice one byte up, the edge byte on top
+            zl = __builtin_amdgcn_alignbit(oh, ol, 8);
+            zh = oh >> 8;
+            if (RAGGED) {
+                const uint64_t eb = (uint64_t)cur.e << esh;
+                zl |= (uint32_t)eb;
+                zh |= (uint32_t)(eb >> 32);
+            } else {
+                zh |= cur.e << 24;
+            }
         } else {
-            zph |= cur.nb << 24;
+            // z-1: the other sublattice one byte down, the edge byte at the bottom
+            zl = (ol << 8) | cur.e;
+            zh = __builtin_amdgcn_alignbit(oh, ol, 24);
         }
-        const uint32_t cl = (zml + zpl + (uint32_t)cur.Yp) + ((uint32_t)cur.Ym + (uint32_t)Wm + (uint32_t)cur.Wn);
-        const uint32_t ch = (zmh + zph + (uint32_t)(cur.Yp >> 32)) +
-                            ((uint32_t)(cur.Ym >> 32) + (uint32_t)(Wm >> 32) + (uint32_t)(cur.Wn >> 32));
-        const uint32_t clsw = (x == 0 ? 0x40404040u : 0u) + (x == Lx - 1 ? 0x80808080u : 0u);
-        // per byte 4 (cnt + 8u) + 64 class
-        uint32_t ilo = ((cl + (wl << 3)) << 2) + clsw;
-        uint32_t ihi = ((ch + (wh << 3)) << 2) + clsw;
-        if (RAGGED) {
-            ilo = (ilo & (uint32_t)L.valid) | (uint32_t)L.padidx;
-            ihi = (ihi & (uint32_t)(L.valid >> 32)) | (uint32_t)(L.padidx >> 32);
-        }
-        ilo >>= 8 * q;
-        ihi >>= 8 * q;
-        uint32_t rnd[4];
-        philox10(g, v.t, v.replica, 0u, v.key0, v.key1, rnd);
-        // a site's byte is 4e (e: table index) and both tables hold 8-byte
-        // entries, so the byte times 2 is the entry's byte offset
-        const uint32_t off[4] = {2u * (ilo & 0xFFu), 2u * ((ilo >> 16) & 0xFFu), 2u * (ihi & 0xFFu),
-                                 2u * ((ihi >> 16) & 0xFFu)};
-        bool acc[4];
-        int dp[4];
+        const uint32_t sl = (uint32_t)cur.S, sh = (uint32_t)(cur.S >> 32);
+        const uint32_t cl = ((ol + zl) + ((uint32_t)cur.yp + (uint32_t)cur.ym)) + ((uint32_t)xm + (uint32_t)cur.xp);
+        const uint32_t ch = ((oh + zh) + ((uint32_t)(cur.yp >> 32) + (uint32_t)(cur.ym >> 32))) +
+                            ((uint32_t)(xm >> 32) + (uint32_t)(cur.xp >> 32));
+        // per byte 8 (8u + cnt): the entry's byte offset in its class's table
+        const uint32_t il = (cl + (sl << 3)) << 3;
+        const uint32_t ih = (ch + (sh << 3)) << 3;
+        const int cls = (x == 0 ? 1 : 0) + (x == Lx - 1 ? 2 : 0);
+        const char *tdc = (const char *)(tb->td + cls * kThrPerClass);
+        const char *thc = (const char *)(tb->thr + cls * kThrPerClass);
+        uint32_t r0[4], r1[4];
+        philox10<0u>(g, v.t, v.replica, 0u, v.key0, v.key1, r0);
+        philox10<2u>(g, v.t, v.replica, 0u, v.key0, v.key1, r1);
+        uint32_t fl = 0, fh = 0;
+        int step = 0;
 #pragma unroll
-        for (int l = 0; l < 4; ++l) {
-            const TD t = *(const TD *)((const char *)tb->td + off[l]);
-            if (NEVER) acc[l] = (uint64_t)rnd[l] < *(const uint64_t *)((const char *)tb->thr + off[l]);
-            else acc[l] = rnd[l] <= t.thr_m1;
-            dp[l] = acc[l] ? t.dpack : 0;
+        for (int b = 0; b < 8; ++b) {
+            const uint32_t w = b < 4 ? il : ih;
+            const uint32_t off = (w >> (8 * (b & 3))) & 0xFFu;
+            const uint32_t u = b < 4 ? r0[b] : r1[b - 4];
+            const TD t = *(const TD *)(tdc + off);
+            bool acc;
+            if (NEVER) acc = (uint64_t)u < *(const uint64_t *)(thc + off);
+            else acc = u <= t.thr_m1;
+            if (RAGGED) acc = acc && (b < nv);
+            step += acc ? t.dpack : 0;
+            if (b < 4) fl |= (acc ? 1u : 0u) << (8 * b);
+            else fh |= (acc ? 1u : 0u) << (8 * (b - 4));
         }
-        const int step = (dp[0] + dp[1]) + (dp[2] + dp[3]);
-        const uint32_t flo = (acc[0] ? 1u : 0u) | (acc[1] ? 0x10000u : 0u);
-        const uint32_t fhi = (acc[2] ? 1u : 0u) | (acc[3] ? 0x10000u : 0u);
-        uint32_t flip_l = flo << (8 * q), flip_h = fhi << (8 * q);
-        if (RAGGED) {
-            flip_l &= (uint32_t)L.valid;
-            flip_h &= (uint32_t)(L.valid >> 32);
-        }
-        st64<COH>(v.spins, xo + L.oc, Wc ^ (((uint64_t)flip_h << 32) | flip_l));
+        st64<COH>(v.spins, own, cur.S ^ (((uint64_t)fh << 32) | fl));
         dsum += step;
         if (first) dfirst = step;
         first = false;
         dlast = step;
-        Wm = Wc;
-        Wc = cur.Wn;
+        // the next plane: its x-1 word is this plane's other sublattice, its
+        // other-sublattice word is this plane's x+1 word
+        xm = O;
+        O = cur.xp;
         if (more) cur = nxt;
-        xo += xstride;
+        rw += XB;
         g += gstep;
         g ^= 1u;
         q ^= 1;
     }
-    // packed sums: dB in the low 16 bits (|sum| < 2^15 for <= kMaxMarch planes)
+    // packed sums: dB in the low 16 bits (|sum| < 2^15 for <= kMaxMarch planes of 8 sites)
     const int dB = (int)(int16_t)(dsum & 0xFFFF), dM = (dsum - dB) >> 16;
     a.dB += dB;
     a.dM += dM;
@@ -924,7 +933,7 @@ __device__ __forceinline__ void slab_stage(const RepView &v, const Entry &en, in
         const int x = (xi & 1) ? Lx - 1 - p : p;
         if ((xi & 1) && x == p) continue;   // the middle plane of an odd Lx pairs with itself
         const int y = phase >= 2 ? 0 : (ri == 0 ? 1 : Ly - 1);
-        if (FMT == ISLF_SPIN_INT8) i8_update_chunk<COH>(v, x, y, j0 + jj, phase & 1, tb->thr, a);
+        if (FMT == ISLF_SPIN_INT8) i8_update_col<COH>(v, x, y, j0 + jj, phase & 1, tb->thr, a);
         else bp_update_word<COH>(v, x, y, j0 + jj, phase & 1, tb->thr, a);
     }
 }
@@ -969,7 +978,7 @@ __device__ __forceinline__ void main_piece(const RepView &v, const Entry &en, in
 {
     const int parity = KIND == KIND_A ? 0 : 1;
     if (FMT == ISLF_SPIN_INT8) {
-        const bool ragged = (v.Lz & 7) != 0;
+        const bool ragged = (v.Lz & 15) != 0;   // a sublattice row ends in a partial column
         if (v.never) {
             if (ragged) i8_march<true, true, COH>(v, en, k_lo, k_hi, parity, tb, a);
             else i8_march<true, false, COH>(v, en, k_lo, k_hi, parity, tb, a);
@@ -1152,28 +1161,32 @@ __global__ __launch_bounds__(kBlock, 4) void k_persistent(const RepDesc *__restr
 __global__ void k_init_i8(const RepDesc *__restrict__ descs, int rep, int mode, const int8_t *__restrict__ host)
 {
     const RepDesc &d = descs[rep];
-    const long nch = (long)d.Lx * d.Ly * d.C;
-    for (long k = (long)blockIdx.x * blockDim.x + threadIdx.x; k < nch; k += (long)gridDim.x * blockDim.x) {
-        const long row = k / d.C;
-        const int j = (int)(k - row * d.C);
-        const int r = (j == d.C - 1) ? d.Lz - 8 * (d.C - 1) : 8;
+    const int Lzh = d.Lz >> 1;
+    // one 8-byte column (row, sublattice q, column k) per step: sites z = 2i + q, i = 8k .. 8k+7
+    const long ncol = (long)d.Lx * d.Ly * 2 * d.K;
+    for (long c = (long)blockIdx.x * blockDim.x + threadIdx.x; c < ncol; c += (long)gridDim.x * blockDim.x) {
+        const long row = c / (2 * d.K);
+        const int rem = (int)(c - row * 2 * d.K);
+        const int q = rem / d.K, k = rem - q * d.K;
+        const int nv = min(8, Lzh - 8 * k);
         uint64_t W = 0;
         if (mode == 0) {
-            for (int q = 0; q < 2; ++q) {
+            for (int h = 0; h < 2; ++h) {
                 uint32_t rnd[4];
-                philox10((((uint32_t)k) << 1) | (uint32_t)q, 0u, d.replica, 1u, d.key0, d.key1, rnd);
+                const uint32_t g = (((uint32_t)(row * d.C + 2 * k + h)) << 1) | (uint32_t)q;
+                philox10(g, 0u, d.replica, 1u, d.key0, d.key1, rnd);
                 for (int l = 0; l < 4; ++l) {
-                    const int pos = q + 2 * l;
-                    if (pos < r) W |= (uint64_t)(1u - (rnd[l] >> 31)) << (8 * pos);
+                    const int b = 4 * h + l;
+                    if (b < nv) W |= (uint64_t)(1u - (rnd[l] >> 31)) << (8 * b);
                 }
             }
         } else if (mode == 1) {
-            for (int pos = 0; pos < r; ++pos) W |= 1ull << (8 * pos);
+            for (int b = 0; b < nv; ++b) W |= 1ull << (8 * b);
         } else if (mode == 3) {
-            const int8_t *src = host + row * d.Lz + 8 * j;
-            for (int pos = 0; pos < r; ++pos) W |= (uint64_t)(src[pos] > 0 ? 1u : 0u) << (8 * pos);
+            const int8_t *src = host + row * d.Lz + q;
+            for (int b = 0; b < nv; ++b) W |= (uint64_t)(src[2 * (8 * k + b)] > 0 ? 1u : 0u) << (8 * b);
         }
-        *(uint64_t *)(d.spins + (size_t)row * d.Lzp + 8 * j) = W;
+        *(uint64_t *)(d.spins + (size_t)row * d.RB + (size_t)q * d.Hp + 8 * k) = W;
     }
 }
 
@@ -1219,8 +1232,9 @@ __global__ void k_export(const RepDesc *__restrict__ descs, int rep, int8_t *__r
     for (int r = blockIdx.x; r < d.Lx * d.Ly; r += gridDim.x) {
         int8_t *o = out + (size_t)r * (size_t)Lz;
         if (d.fmt == ISLF_SPIN_INT8) {
-            const uint8_t *src = d.spins + (size_t)r * d.Lzp;
-            for (int z = threadIdx.x; z < Lz; z += blockDim.x) o[z] = src[z] ? (int8_t)1 : (int8_t)-1;
+            const uint8_t *src = d.spins + (size_t)r * d.RB;
+            for (int z = threadIdx.x; z < Lz; z += blockDim.x)
+                o[z] = src[(z & 1) * d.Hp + (z >> 1)] ? (int8_t)1 : (int8_t)-1;
         } else {
             const uint32_t *row = (const uint32_t *)d.spins + (size_t)r * 2 * d.Wq;
             for (int z = threadIdx.x; z < Lz; z += blockDim.x)
@@ -1319,7 +1333,7 @@ __global__ __launch_bounds__(256) void k_layer_profile(const RepDesc *__restrict
     const RepDesc &d = descs[rep];
     const int Lz = d.Lz;
     const bool i8 = d.fmt == ISLF_SPIN_INT8;
-    const uint32_t rw = i8 ? (uint32_t)(d.Lzp >> 2) : (uint32_t)(2 * d.Wq);   // words per row
+    const uint32_t rw = i8 ? (uint32_t)(d.RB >> 2) : (uint32_t)(2 * d.Wq);   // words per row
     const long rows = (long)d.Lx * (long)d.Ly;
     const uint32_t R = rw >= (uint32_t)kProfileWords ? 1u : (uint32_t)kProfileWords / rw;
     const long r0 = (long)blockIdx.x * R;
@@ -1334,8 +1348,11 @@ __global__ __launch_bounds__(256) void k_layer_profile(const RepDesc *__restrict
         const uint32_t row = k / rw, col = k - row * rw;
         uint32_t v = base[k], up;
         if (i8) {
-            const int z0 = 4 * (int)col;
-            if (z0 + 4 > Lz) v &= (z0 >= Lz) ? 0u : ((1u << (8 * (Lz - z0))) - 1u);
+            // byte i0 .. i0+3 of sublattice row q; the padding past Lz/2 is masked
+            const uint32_t hw = (uint32_t)d.Hp >> 2;
+            const int i0 = 4 * (int)(col < hw ? col : col - hw);
+            const int nb = min(4, (Lz >> 1) - i0);
+            if (nb < 4) v &= nb <= 0 ? 0u : ((1u << (8 * nb)) - 1u);
             up = __builtin_amdgcn_sad_u8(v, 0u, 0u);
         } else {
             const int w = (int)col < Wq ? (int)col : (int)col - Wq;

@@ -31,7 +31,7 @@ def built():
 
 
 def columns(Lz, fmt):
-    return (Lz + 7) // 8 if fmt == islf.INT8 else (Lz + 63) // 64
+    return (Lz + 15) // 16 if fmt == islf.INT8 else (Lz + 63) // 64
 
 
 def main_sites(item, shape, Ly, J):
