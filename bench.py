@@ -60,12 +60,19 @@ def parse():
     ap.add_argument("--steps", type=int, default=2000)
     ap.add_argument("--warmup", type=int, default=200)
     ap.add_argument("--chunk", type=int, default=50, help="sweeps per captured graph launch")
+    ap.add_argument("--min-warmup-s", type=float, default=0.5,
+                    help="untimed graph replays continue until this many seconds of warm-up have passed")
     ap.add_argument("--groups", type=int, default=0,
                     help="concurrent replica groups of the batched form (0: automatic, 1: one launch chain)")
+    ap.add_argument("--grid", type=int, default=0,
+                    help="workgroups per launch of the headline form (0: the library's default)")
+    ap.add_argument("--tile", type=int, default=-1,
+                    help="tile variant of every replica of the headline form (-1: the library's default)")
     ap.add_argument("--form", choices=["persistent", "batched", "plain"], default="batched")
     ap.add_argument("--fmt", choices=["int8", "bitpack"], default="bitpack")
     ap.add_argument("--no-extras", action="store_true", help="skip the other forms and formats")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--no-aux", action="store_true", help="skip the layer-profile and host hand-over figures")
     ap.add_argument("--cpu-sweeps", type=int, default=10)
     ap.add_argument("--no-configs", action="store_true",
                     help="skip the batched-TI, uneven-autotuned and serving configurations")
@@ -88,19 +95,22 @@ def replicas(islf, n=None):
                          seed=SEED + i, replica=i, init=islf.INIT_RANDOM) for i in range(n)]
 
 
-def run_form(islf, torch, form, fmt, steps, warmup, chunk, n_reps=None, groups=0, reps=None, autotune=0):
+def run_form(islf, torch, form, fmt, steps, warmup, chunk, n_reps=None, groups=0, reps=None, autotune=0, grid=0,
+             tile=-1, min_warm_s=0.5):
     """Times `steps` sweeps of a batch in one execution form: graph replays of
-    `chunk` sweeps (plus eager sweeps for a remainder), after one untimed
-    replay of the same graph and the rest of the warm-up.  HIP events on the
-    context's stream bracket the timed region (the group streams fork from
-    and join back to it inside it)."""
+    `chunk` sweeps (plus eager sweeps for a remainder), after the warm-up:
+    at least `warmup` sweeps, at least one untimed replay of the same graph,
+    and untimed replays until `min_warm_s` seconds have passed (the GPU
+    raises its clocks over the first fraction of a second of work).  HIP
+    events on the context's stream bracket the timed region (the group
+    streams fork from and join back to it inside it)."""
     mode = {"persistent": islf.EXEC_PERSISTENT, "batched": islf.EXEC_BATCHED, "plain": islf.EXEC_PLAIN}[form]
     f = {"int8": islf.INT8, "bitpack": islf.BITPACK}[fmt]
     reps = replicas(islf, n_reps) if reps is None else reps
     chunk = max(1, min(chunk, steps))
     n_warm = max(1, warmup // chunk)
     warm_rest = max(0, warmup - n_warm * chunk)
-    ctx = islf.Context(reps, spin_format=f, obs_capacity=steps + n_warm * chunk + warm_rest + 64, exec_mode=mode)
+    ctx = islf.Context(reps, spin_format=f, obs_capacity=steps + chunk + 64, exec_mode=mode)
     try:
         tuned = 0.0
         if autotune:
@@ -109,12 +119,24 @@ def run_form(islf, torch, form, fmt, steps, warmup, chunk, n_reps=None, groups=0
             tuned = time.perf_counter() - t
         if groups:
             ctx.set_groups(groups)
+        if grid:
+            ctx.set_grid(grid)
+        if tile >= 0:
+            for i in range(len(reps)):
+                ctx.set_tile(i, tile)
         ctx.capture(chunk)
         # warm-up: always one untimed replay of the graph (the first replay of
-        # a new graph is slower), then eager sweeps for the remainder
+        # a new graph is slower), eager sweeps for the remainder, then replays
+        # until the clocks are up
+        tw = time.perf_counter()
         ctx.replay(n_warm)
         if warm_rest:
             ctx.sweep(warm_rest)
+        torch.cuda.synchronize()
+        while time.perf_counter() - tw < min_warm_s:
+            ctx.replay(1)
+            n_warm += 1
+            torch.cuda.synchronize()
         n_launch = steps // chunk
         rest = steps - n_launch * chunk
         s = ctx.stream
@@ -278,7 +300,7 @@ def config_figures(islf, torch, steps, warmup, chunk, serve_requests, serve_budg
     ti = {}
     for form, fmt in (("batched", "bitpack"), ("batched", "int8"), ("persistent", "bitpack"),
                       ("persistent", "int8")):
-        r = run_form(islf, torch, form, fmt, st, wu, min(chunk, 50), reps=ti_replicas(islf))
+        r = run_form(islf, torch, form, fmt, st, wu, min(chunk, 50), reps=ti_replicas(islf), min_warm_s=0.2)
         ti[f"{form}_{fmt}"] = round(rate(r), 2)
         print(f"# TI batch {form}/{fmt}: { {k: v for k, v in r.items() if k != 'ctx_means'} }", file=sys.stderr,
               flush=True)
@@ -292,12 +314,13 @@ def config_figures(islf, torch, steps, warmup, chunk, serve_requests, serve_budg
                       "(short chains: a throughput check, not a physics result)")
     out["ti_64x40x120x120"] = ti
     un = {}
-    r = run_form(islf, torch, "batched", "int8", st, wu, min(chunk, 50), reps=uneven_replicas(islf), autotune=4)
+    r = run_form(islf, torch, "batched", "int8", st, wu, min(chunk, 50), reps=uneven_replicas(islf), autotune=4,
+                 min_warm_s=0.2)
     un["batched_int8_autotuned"] = round(rate(r), 2)
     un["autotune_s"] = r.get("autotune_s")
     print(f"# uneven batch int8 autotuned: { {k: v for k, v in r.items() if k != 'ctx_means'} }", file=sys.stderr,
           flush=True)
-    r = run_form(islf, torch, "batched", "bitpack", st, wu, min(chunk, 50), reps=uneven_replicas(islf))
+    r = run_form(islf, torch, "batched", "bitpack", st, wu, min(chunk, 50), reps=uneven_replicas(islf), min_warm_s=0.2)
     un["batched_bitpack"] = round(rate(r), 2)
     un["workload"] = (f"96 replicas, Lx in {{20,40,80}} x Ly=Lz in {{64,128,256}}, T in {{2,2.5,3,3.5,4}}, "
                       f"|h1| in {{0.25,0.5,0.75}}, 125,583,360 sites; timed over {st} sweeps")
@@ -420,7 +443,9 @@ def main():
     def brief(r):
         return {k: v for k, v in r.items() if k != "ctx_means"}
 
-    main_run = run_form(islf, torch, args.form, args.fmt, args.steps, args.warmup, args.chunk, groups=args.groups)
+    WARM_S = args.min_warmup_s
+    main_run = run_form(islf, torch, args.form, args.fmt, args.steps, args.warmup, args.chunk, groups=args.groups,
+                        grid=args.grid, tile=args.tile, min_warm_s=WARM_S)
     print(f"# {args.form}/{args.fmt}: {brief(main_run)}", file=sys.stderr, flush=True)
     value = rate(main_run)
     # the same form as one launch chain over all replicas, timed the same way:
@@ -430,7 +455,7 @@ def main():
         chain_run = main_run
     else:
         chain_run = run_form(islf, torch, args.form, args.fmt, min(args.steps, 400), min(args.warmup, 100),
-                             args.chunk, groups=1)
+                             args.chunk, groups=1, tile=args.tile, min_warm_s=WARM_S)
         print(f"# {args.form}/{args.fmt} one launch chain: {brief(chain_run)}", file=sys.stderr, flush=True)
 
     forms = {}
@@ -440,12 +465,13 @@ def main():
                           ("persistent", "int8")):
             if (form, fmt) == (args.form, args.fmt):
                 continue
-            r = run_form(islf, torch, form, fmt, min(args.steps, 100), min(args.warmup, 50), min(args.chunk, 50))
+            r = run_form(islf, torch, form, fmt, min(args.steps, 100), min(args.warmup, 50), min(args.chunk, 50),
+                         min_warm_s=0.2)
             forms[f"{form}_{fmt}"] = round(rate(r), 2)
             print(f"# {form}/{fmt}: {brief(r)}", file=sys.stderr, flush=True)
         # a batch larger than the 256 MB last-level cache: 8 int8 replicas, 369 MB of spins
         r = run_form(islf, torch, "batched", "int8", min(args.steps, 50), min(args.warmup, 50), min(args.chunk, 50),
-                     n_reps=8)
+                     n_reps=8, min_warm_s=0.2)
         forms["batched_int8_8x46M_369MB"] = round(rate(r), 2)
         print(f"# batched/int8 x8: {brief(r)}", file=sys.stderr, flush=True)
 
@@ -481,10 +507,12 @@ def main():
                 "valu": committed_valu(args.fmt),
                 "limiter": "VALU issue: Philox4x32-10 costs 5 64-bit products and 5 xors per update"}
 
-    prof = layer_profile_rate(islf, torch)
-    print(f"# layer profile: {prof}", file=sys.stderr, flush=True)
-    hio = host_io_rate(islf, torch, args.fmt, main_run["sweeps_per_launch"], main_run["ms_per_sweep"])
-    print(f"# host io: {hio}", file=sys.stderr, flush=True)
+    prof = hio = None
+    if not args.no_aux:
+        prof = layer_profile_rate(islf, torch)
+        print(f"# layer profile: {prof}", file=sys.stderr, flush=True)
+        hio = host_io_rate(islf, torch, args.fmt, main_run["sweeps_per_launch"], main_run["ms_per_sweep"])
+        print(f"# host io: {hio}", file=sys.stderr, flush=True)
 
     cpu = None if args.no_cpu else cpu_baseline(args.cpu_sweeps)
     line = {

@@ -11,8 +11,10 @@ of Eq. 7 / Eq. 19, thermodynamic integration of Eq. 9 / Eq. 22.
 """
 from __future__ import annotations
 
+import atexit
 import ctypes as C
 import os
+import weakref
 from dataclasses import dataclass, field
 
 import numpy as np
@@ -177,6 +179,23 @@ def _torch():
     return torch
 
 
+# Contexts still open when the interpreter exits are closed by an exit hook,
+# registered after torch is imported so that it runs before torch's own exit
+# hooks: their device memory goes back through torch's allocator while it
+# still exists, and their graphs, streams and events are released before
+# the HIP runtime shuts down.
+_open_contexts: "weakref.WeakSet[Context]" = weakref.WeakSet()
+_exit_hook = False
+
+
+def _close_open_contexts():
+    for ctx in list(_open_contexts):
+        try:
+            ctx.close()
+        except Exception:
+            pass
+
+
 class Context:
     """A set of replicas on one GPU (islf_ctx)."""
 
@@ -202,6 +221,11 @@ class Context:
             _check(lib().islf_create(arr, len(reps), spin_format, obs_capacity,
                                      C.c_void_p(self.stream.cuda_stream), C.byref(h)))
         self._h = h
+        global _exit_hook
+        if not _exit_hook:
+            atexit.register(_close_open_contexts)
+            _exit_hook = True
+        _open_contexts.add(self)
         self.set_exec(exec_mode)
 
     # lifetime -------------------------------------------------------------
