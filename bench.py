@@ -159,6 +159,8 @@ def run_form(islf, torch, form, fmt, steps, warmup, chunk, n_reps=None, groups=0
                    grid=ctx.get_grid(), sites=sum(r.N for r in reps), ctx_means=None)
         if autotune:
             out["autotune_s"] = round(tuned, 2)
+            out["tuned"] = {"groups": ctx.get_groups() if form == "batched" else 1, "grid": ctx.get_grid(),
+                            "taper": ctx.get_taper(), "tiles": sorted({ctx.get_tile(i) for i in range(len(reps))})}
         out["ctx_means"] = ctx.means(done - steps, steps)
         return out
     finally:
@@ -309,6 +311,13 @@ def config_figures(islf, torch, steps, warmup, chunk, serve_requests, serve_budg
             h = np.arange(64) / 63.0
             cum = islf.integrate(h, m[:, 3], m[:, 4], -1.0, 1.0, 1.0 / (120 * 120))
             ti["delta_f1_at_h1_1"] = float(cum[-1])
+    for form in ("batched", "persistent"):
+        r = run_form(islf, torch, form, "bitpack", st, wu, min(chunk, 50), reps=ti_replicas(islf), autotune=4,
+                     min_warm_s=0.2)
+        ti[f"{form}_bitpack_autotuned"] = round(rate(r), 2)
+        ti[f"{form}_bitpack_tuned"] = r.get("tuned")
+        print(f"# TI batch {form}/bitpack autotuned: { {k: v for k, v in r.items() if k != 'ctx_means'} }",
+              file=sys.stderr, flush=True)
     ti["workload"] = ("64 replicas of 40x120x120 GAPBC, T=3, h1=r/63, hn=-h1, seeds 14115588+r; "
                       f"timed over {st} sweeps; delta_f1 = trapezoid of -(m1 - mn) over h1 after the timed sweeps "
                       "(short chains: a throughput check, not a physics result)")
@@ -318,6 +327,7 @@ def config_figures(islf, torch, steps, warmup, chunk, serve_requests, serve_budg
                  min_warm_s=0.2)
     un["batched_int8_autotuned"] = round(rate(r), 2)
     un["autotune_s"] = r.get("autotune_s")
+    un["tuned"] = r.get("tuned")
     print(f"# uneven batch int8 autotuned: { {k: v for k, v in r.items() if k != 'ctx_means'} }", file=sys.stderr,
           flush=True)
     r = run_form(islf, torch, "batched", "bitpack", st, wu, min(chunk, 50), reps=uneven_replicas(islf), min_warm_s=0.2)

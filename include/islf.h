@@ -291,13 +291,32 @@ islf_status islf_run_graph(islf_ctx *ctx, uint32_t n_replays);
 /* Number of tile variants of the update kernels, and the variant in use for
  * a replica.  Every variant computes the same result; they differ only in
  * the thread-to-site mapping.  islf_set_tile changes one replica's variant
- * (rebuilding work lists); islf_autotune times each variant on the live
- * batch for `sweeps` sweeps per trial (restoring the spins afterwards, so
- * results are unaffected) and keeps the fastest per size class. */
+ * (rebuilding work lists).
+ * islf_autotune tunes the live batch in two steps, each trial timed over
+ * `sweeps` sweeps after one untimed sweep: (1) per size class, every tile
+ * variant (the class's replicas alone, in a batched plan of their own), the
+ * fastest kept; (2) for the context's execution form, the launch
+ * configuration on the whole batch: batched, concurrent groups 1..4 x
+ * workgroups per launch (1/2, 1, 3/2 of the default) x share taper
+ * (0, 0.1, 0.2); persistent, grids of up to one workgroup per CU below the
+ * co-residency bound x the same tapers; the fastest is kept (islf_get_groups,
+ * islf_get_grid, islf_get_taper report it).  Spins, records and sweep
+ * counters are restored afterwards, so results are unaffected.  Synchronises.
+ * Errors: EINVAL, ENOMEM (backups), EDEVICE. */
 islf_status islf_num_tiles(int32_t spin_format, int32_t *n);
 islf_status islf_get_tile(const islf_ctx *ctx, int32_t rep, int32_t *tile);
 islf_status islf_set_tile(islf_ctx *ctx, int32_t rep, int32_t tile);
 islf_status islf_autotune(islf_ctx *ctx, uint32_t sweeps);
+
+/* Share taper of the batched and persistent launch plans: the work of a
+ * launch is cut into per-workgroup shares that shrink linearly with the
+ * dispatch rank by up to +-taper (later workgroups get less, against the
+ * uneven progress of the workgroups resident on one CU).  A negative value
+ * restores the built-in one (0 bit-packed and 0.1 int8 batched, 0.1
+ * persistent).  Every choice computes the same result; changing it
+ * invalidates a captured graph.  Errors: EINVAL (NULL, taper >= 1). */
+islf_status islf_set_taper(islf_ctx *ctx, double taper);
+islf_status islf_get_taper(const islf_ctx *ctx, double *taper);
 
 /* Launch-plan preview, host only (no device, no context): the work items of
  * n_reps replicas (tile variant `tile`, or each replica's default with -1)

@@ -171,12 +171,31 @@ def beta_integral(beta, u) -> np.ndarray:
     return out
 
 
+def ground_state_reference(beta0: float, J: float, Lx: int, Lz: int, Ly: int | None = None) -> float:
+    """The low-temperature reference of Eq. 19 for an antiperiodic minus a
+    periodic film (free x surfaces, no fields): at beta0 J = 10 the free
+    energy is close to the ground-state energy U0 (Sec. II.C, after Eq. 19),
+    and the antiperiodic ground state differs from the periodic one by one
+    flat interface across the film, Lx Lz bonds each 2 J dearer, so
+    beta0 delta F(beta0) = beta0 * 2 J Lx Lz.  With Ly given, the
+    interface-position entropy is included as well: the antiperiodic ground
+    state is 2 Ly-fold degenerate (Ly positions, two orientations), the
+    periodic one 2-fold, which lowers beta0 delta F by ln Ly; F = U0 drops
+    this term, which is small beside beta0 * 2 J Lx Lz."""
+    ref = float(beta0) * 2.0 * float(J) * float(Lx) * float(Lz)
+    if Ly is not None:
+        ref -= math.log(float(Ly))
+    return ref
+
+
 def delta_free_energy(beta, u_apbc, u_pbc, beta_dF0: float = 0.0) -> np.ndarray:
     """Eq. 20 from Eq. 19 applied to both films: beta delta F(beta) =
     beta_0 delta F(beta_0) + integral_{beta_0}^{beta} (U_APBC - U_PBC) d beta',
     returned as delta F(beta) = F_APBC - F_PBC at every ladder point.  The
     reference difference beta_0 delta F(beta_0) is 0 for a reference in the
-    disordered phase (beta_0 < beta_c), where no interface exists."""
+    disordered phase (beta_0 < beta_c), where no interface exists, and
+    ground_state_reference(beta_0, ...) for the low-temperature reference
+    beta_0 J = 10; the ladder may run upwards or downwards from beta_0."""
     b = np.asarray(beta, dtype=np.float64)
     d = np.asarray(u_apbc, dtype=np.float64) - np.asarray(u_pbc, dtype=np.float64)
     return (beta_dF0 + beta_integral(b, d)) / b

@@ -227,6 +227,7 @@ struct islf_ctx {
     int resident_slots = 0;    // workgroups of the sweep kernels resident at once on the device
     int sweep_slots = 0;       // default workgroups per sweep launch (2 per resident slot)
     int grid_override = 0;     // workgroups per batched / plain launch (0: sweep_slots)
+    double taper_override = -1.0;   // share taper of the batched and persistent plans (< 0: the built-in one)
     int persistent_grid = 0;   // workgroups of the persistent kernel's cooperative launch
     int persistent_bound = 0;  // co-residency bound computed for it on this device
     double *noalloc_scratch = nullptr;   // this device's copy of the means scratch array
@@ -683,7 +684,7 @@ static islf_status prepare_groups(islf_ctx *c)
             S.insert(S.end(), c->reps[r].slab.begin(), c->reps[r].slab.end());
             M.insert(M.end(), c->reps[r].main.begin(), c->reps[r].main.end());
         }
-        st = build_plan(c, c->group_plan[g], S, M, launch_grid(c, ISLF_EXEC_BATCHED));
+        st = build_plan(c, c->group_plan[g], S, M, launch_grid(c, ISLF_EXEC_BATCHED), c->taper_override);
         if (st != ISLF_OK) return st;
     }
     while ((int)c->side_stream.size() < G - 1) {
@@ -715,7 +716,8 @@ static islf_status prepare_plans(islf_ctx *c, int exec)
     if (exec == ISLF_EXEC_BATCHED && !c->batched.valid) {
         std::vector<Entry> S, M;
         lists(c->live, S, M);
-        return build_plan(c, c->batched, S, M, c->grid_override ? c->grid_override : c->sweep_slots);
+        return build_plan(c, c->batched, S, M, c->grid_override ? c->grid_override : c->sweep_slots,
+                          c->taper_override);
     }
     if (exec == ISLF_EXEC_PERSISTENT && !c->persistent.valid) {
         std::vector<Entry> S, M;
@@ -724,7 +726,8 @@ static islf_status prepare_plans(islf_ctx *c, int exec)
         if (grid > c->persistent_bound)
             return fail(ISLF_ERANGE, "persistent grid %d exceeds the co-residency bound %d of this device", grid,
                         c->persistent_bound);
-        return build_plan(c, c->persistent, S, M, grid, kPersistentTaper);
+        return build_plan(c, c->persistent, S, M, grid,
+                          c->taper_override >= 0.0 ? c->taper_override : kPersistentTaper);
     }
     if (exec == ISLF_EXEC_PLAIN) {
         if (c->plain.size() < c->reps.size()) c->plain.resize(c->reps.size());
@@ -1728,6 +1731,102 @@ extern "C" islf_status islf_autotune(islf_ctx *ctx, uint32_t sweeps)
         islf_status rs = restore();
         if (rs != ISLF_OK) result = rs;
     }
+    // the launch configuration of the context's form on the whole batch:
+    // batched: concurrent groups x workgroups per launch x share taper;
+    // persistent: grid (up to the co-residency bound) x taper.  Each trial
+    // captures `sweeps` sweeps as graphs and times the second of two
+    // replays (eager launches on the default stream); the chains advance
+    // during the trials and are restored once afterwards.
+    if (result == ISLF_OK && !ctx->live.empty() &&
+        (ctx->exec == ISLF_EXEC_BATCHED || ctx->exec == ISLF_EXEC_PERSISTENT)) {
+        ctx->dirty = true;
+        result = sync_tables(ctx);
+        const int keep_groups = ctx->groups_req, keep_grid = ctx->grid_override;
+        const double keep_taper = ctx->taper_override;
+        struct Trial { int groups, grid; double taper; };
+        std::vector<Trial> trials;
+        const double tapers[] = {0.0, 0.1, 0.2};
+        if (ctx->exec == ISLF_EXEC_BATCHED) {
+            const int nl = (int)ctx->live.size();
+            for (int G = 1; G <= std::min(4, nl); ++G) {
+                const int base = G == 1 ? ctx->sweep_slots : std::max(64, (3 * ctx->resident_slots + G) / (2 * G));
+                for (double f : {0.5, 1.0, 1.5})
+                    for (double tp : tapers) trials.push_back(Trial{G, std::max(32, (int)(base * f + 0.5)), tp});
+            }
+        } else {
+            // up to one workgroup per CU below the bound, like the default grid
+            const int per_cu = std::max(1, ctx->persistent_bound / std::max(1, ctx->num_cu));
+            const int top = std::max(1, per_cu - 1);
+            for (int k = std::max(1, top - 2); k <= top; ++k)
+                for (double tp : tapers)
+                    trials.push_back(Trial{0, std::min(ctx->num_cu * k, ctx->persistent_bound), tp});
+        }
+        hipEvent_t e0 = nullptr, e1 = nullptr;
+        if (result == ISLF_OK && (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess))
+            result = fail(ISLF_EDEVICE, "cannot create events");
+        double best = 1e300;
+        Trial best_t{keep_groups, keep_grid, keep_taper};
+        for (const Trial &t : trials) {
+            if (result != ISLF_OK) break;
+            ctx->groups_req = t.groups ? t.groups : keep_groups;
+            ctx->grid_override = t.grid;
+            ctx->taper_override = t.taper;
+            ctx->groups_valid = false;
+            ctx->batched.valid = false;
+            ctx->persistent.valid = false;
+            result = prepare_plans(ctx, ctx->exec);
+            if (result != ISLF_OK) break;
+            float ms = 0.f;
+            hipError_t e = hipSuccess;
+            if (ctx->stream) {
+                // as a captured graph replays it (host launch costs excluded):
+                // one untimed replay, one timed
+                result = islf_graph_capture(ctx, sweeps);
+                if (result != ISLF_OK) break;
+                const int G = (int)ctx->graph_execs.size();
+                for (int rep = 0; rep < 2 && e == hipSuccess; ++rep) {
+                    if (rep == 1) e = hipEventRecord(e0, ctx->stream);
+                    if (e == hipSuccess && G > 1) e = fork_groups(ctx, G);
+                    for (int g = 0; g < G && e == hipSuccess; ++g)
+                        e = hipGraphLaunch(ctx->graph_execs[g], group_stream(ctx, g));
+                    if (e == hipSuccess && G > 1) e = join_groups(ctx, G);
+                }
+                destroy_graphs(ctx);
+            } else {
+                result = enqueue_sweeps(ctx, 1);
+                if (result != ISLF_OK) break;
+                e = hipEventRecord(e0, ctx->stream);
+                if (e == hipSuccess) {
+                    result = enqueue_sweeps(ctx, sweeps);
+                    if (result != ISLF_OK) break;
+                }
+            }
+            if (e == hipSuccess) e = hipEventRecord(e1, ctx->stream);
+            if (e == hipSuccess) e = hipEventSynchronize(e1);
+            if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+            if (e != hipSuccess) {
+                result = fail(ISLF_EDEVICE, "autotune trial failed: %s", hipGetErrorString(e));
+                break;
+            }
+            if (ms < best) {
+                best = ms;
+                best_t = t;
+            }
+        }
+        if (e0) (void)hipEventDestroy(e0);
+        if (e1) (void)hipEventDestroy(e1);
+        ctx->groups_req = (result == ISLF_OK && best_t.groups) ? best_t.groups : keep_groups;
+        ctx->grid_override = result == ISLF_OK ? best_t.grid : keep_grid;
+        ctx->taper_override = result == ISLF_OK ? best_t.taper : keep_taper;
+        ctx->groups_valid = false;
+        ctx->batched.valid = false;
+        ctx->persistent.valid = false;
+        ctx->graph_valid = false;
+        if (result == ISLF_OK) {
+            islf_status rs = restore();
+            if (rs != ISLF_OK) result = rs;
+        }
+    }
     if (hipStreamSynchronize(ctx->stream) != hipSuccess && result == ISLF_OK)
         result = fail(ISLF_EDEVICE, "autotune synchronisation failed");
     for (void *b : backup) dev_free(ctx, b);
@@ -1909,5 +2008,25 @@ extern "C" islf_status islf_testing_raise_barrier_error(islf_ctx *ctx)
     const unsigned long long one = 1;
     HIP_TRY(hipMemcpyAsync(&ctx->d_sync->error.v, &one, sizeof one, hipMemcpyHostToDevice, ctx->stream));
     HIP_TRY(hipStreamSynchronize(ctx->stream));
+    return ISLF_OK;
+}
+
+extern "C" islf_status islf_set_taper(islf_ctx *ctx, double taper)
+{
+    if (!ctx) return fail(ISLF_EINVAL, "NULL context");
+    if (!(taper < 1.0)) return fail(ISLF_EINVAL, "taper must be below 1 (got %g)", taper);
+    ctx->taper_override = taper < 0.0 ? -1.0 : taper;
+    ctx->batched.valid = false;
+    ctx->persistent.valid = false;
+    ctx->groups_valid = false;
+    ctx->graph_valid = false;
+    return ISLF_OK;
+}
+
+extern "C" islf_status islf_get_taper(const islf_ctx *ctx, double *taper)
+{
+    if (!ctx || !taper) return fail(ISLF_EINVAL, "NULL argument");
+    if (ctx->taper_override >= 0.0) *taper = ctx->taper_override;
+    else *taper = ctx->exec == ISLF_EXEC_PERSISTENT ? kPersistentTaper : tail_taper(ctx->fmt);
     return ISLF_OK;
 }

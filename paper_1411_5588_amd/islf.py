@@ -125,6 +125,8 @@ def lib():
             "islf_phase_timings": [vp, u32, vp, vp],
             "islf_replica_means": [vp, i32, u64, u32, vp],
             "islf_device_bytes": [vp, P(u64), P(u64)],
+            "islf_set_taper": [vp, dbl],
+            "islf_get_taper": [vp, P(dbl)],
             "islf_testing_raise_barrier_error": [vp],
         }
         for name, args in sig.items():
@@ -385,6 +387,15 @@ class Context:
         t, r = C.c_uint64(), C.c_uint64()
         _check(lib().islf_device_bytes(self._h, C.byref(t), C.byref(r)))
         return t.value, r.value
+
+    def set_taper(self, taper: float):
+        """Share taper of the batched and persistent plans (< 0: built-in)."""
+        _check(lib().islf_set_taper(self._h, taper))
+
+    def get_taper(self) -> float:
+        t = C.c_double()
+        _check(lib().islf_get_taper(self._h, C.byref(t)))
+        return t.value
 
     def get_grid(self) -> int:
         n = C.c_int32()

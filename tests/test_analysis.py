@@ -109,9 +109,9 @@ def test_line_tension_balance():
     assert np.allclose(got, dtau, rtol=0, atol=1e-12)
 
 
-def _exact_ladder(shape, ybc, betas):
+def _exact_ladder(shape, ybc, betas, J=1.0):
     S = X.all_states(*shape)
-    E = X.energies(X.observables(S, ybc), 1.0, 0.0, 0.0, 0.0)
+    E = X.energies(X.observables(S, ybc), J, 0.0, 0.0, 0.0)
     U, lnZ = [], []
     for b in betas:
         a = -b * E
@@ -138,3 +138,41 @@ def test_delta_free_energy_matches_enumeration():
         errs.append(np.max(np.abs(dF - exact)[n // 10:]) / np.max(np.abs(exact)))
     assert errs[1] < 5e-6
     assert 3.5 < errs[0] / errs[1] < 4.5
+
+
+@pytest.mark.parametrize("shape", [(1, 3, 4), (2, 3, 2), (1, 4, 4), (2, 4, 2)])
+def test_ground_state_reference_matches_enumeration(shape):
+    """Eq. 19's low-temperature reference: at beta_0 J = 10 the exact
+    beta_0 (F_APBC - F_PBC) = -(ln Z_APBC - ln Z_PBC) equals beta_0 2 J Lx Lz
+    minus the interface-position entropy ln Ly, up to terms of order
+    exp(-beta_0 * (cheapest excitation)), and within ln Ly of the paper's
+    F = U0."""
+    Lx, Ly, Lz = shape
+    for J in (1.0, 0.7):
+        b0 = 10.0 / J
+        _, lza = _exact_ladder(shape, X.APBC, [b0], J=J)
+        _, lzp = _exact_ladder(shape, X.PBC, [b0], J=J)
+        exact = -(lza[0] - lzp[0])
+        ref = A.ground_state_reference(b0, J, Lx, Lz, Ly)
+        assert abs(exact - ref) < 1e-6 * abs(ref), (exact, ref)
+        assert abs(exact - A.ground_state_reference(b0, J, Lx, Lz)) <= np.log(Ly) + 1e-6
+
+
+def test_delta_free_energy_from_the_ground_state_reference():
+    """The beta path of Eq. 19 run downwards from beta_0 J = 10 to the ordered
+    phase with the ground-state reference reproduces -(ln Z_APBC - ln Z_PBC)
+    / beta from enumeration, and the trapezoid error falls fourfold when the
+    ladder is refined."""
+    shape = (1, 4, 4)
+    Lx, Ly, Lz = shape
+    errs = []
+    for n in (1201, 2401):
+        # dense where U changes (small beta), sparse where it is flat
+        betas = np.concatenate([np.linspace(10.0, 2.0, n // 6, endpoint=False), np.linspace(2.0, 0.4, n - n // 6)])
+        Ua, lza = _exact_ladder(shape, X.APBC, betas)
+        Up, lzp = _exact_ladder(shape, X.PBC, betas)
+        dF = A.delta_free_energy(betas, Ua, Up, beta_dF0=A.ground_state_reference(betas[0], 1.0, Lx, Lz, Ly))
+        exact = -(lza - lzp) / betas
+        errs.append(np.max(np.abs(dF - exact)) / np.max(np.abs(exact)))
+    assert errs[1] < 1e-5
+    assert 3.0 < errs[0] / errs[1] < 5.0

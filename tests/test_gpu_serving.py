@@ -125,11 +125,30 @@ def test_autotune_changes_speed_not_results():
             ctx.sweep(3)
             ctx.autotune(2)
             tiles = [ctx.get_tile(i) for i in range(len(ps))]
+            taper, groups, grid = ctx.get_taper(), ctx.get_groups(), ctx.get_grid()
             ctx.sweep(5)
             recs = [ctx.measure(i, 0, 8) for i in range(len(ps))]
             t = [ctx.sweep_count(i) for i in range(len(ps))]
         assert t == [8] * len(ps)
         assert len(set(tiles[:3])) == 1
+        assert taper in (0.0, 0.1, 0.2) and 1 <= groups <= 4 and grid >= 32
         outs = parallel_map(lambda p: oracle_trajectory(p, 8)[1], ps)
         for rec, o in zip(recs, outs):
             assert np.array_equal(rec, o)
+
+
+def test_autotune_persistent_launch_keeps_results():
+    ps = [dict(Lx=20, Ly=64, Lz=64, ybc=islf.GAPBC, beta=0.4, h1=0.25, hn=-0.25, seed=s, replica=s)
+          for s in range(4)]
+    with islf.Context([islf.Replica(**p) for p in ps], spin_format=islf.BITPACK, obs_capacity=64,
+                      exec_mode=islf.EXEC_PERSISTENT) as ctx:
+        default = ctx.get_grid()
+        ctx.sweep(2)
+        ctx.autotune(2)
+        assert 0 < ctx.get_grid() <= default and ctx.get_taper() in (0.0, 0.1, 0.2)
+        ctx.capture(3)
+        ctx.replay(2)
+        recs = [ctx.measure(i, 0, 8) for i in range(len(ps))]
+    outs = parallel_map(lambda p: oracle_trajectory(p, 8)[1], ps)
+    for rec, o in zip(recs, outs):
+        assert np.array_equal(rec, o)
