@@ -96,7 +96,7 @@ def replicas(islf, n=None):
 
 
 def run_form(islf, torch, form, fmt, steps, warmup, chunk, n_reps=None, groups=0, reps=None, autotune=0, grid=0,
-             tile=-1, min_warm_s=0.5):
+             tile=-1, min_warm_s=0.5, barriers=None):
     """Times `steps` sweeps of a batch in one execution form: graph replays of
     `chunk` sweeps (plus eager sweeps for a remainder), after the warm-up:
     at least `warmup` sweeps, at least one untimed replay of the same graph,
@@ -113,6 +113,8 @@ def run_form(islf, torch, form, fmt, steps, warmup, chunk, n_reps=None, groups=0
     ctx = islf.Context(reps, spin_format=f, obs_capacity=steps + chunk + 64, exec_mode=mode)
     try:
         tuned = 0.0
+        if barriers is not None:
+            ctx.set_barriers(barriers)
         if autotune:
             t = time.perf_counter()
             ctx.autotune(autotune)
@@ -161,6 +163,8 @@ def run_form(islf, torch, form, fmt, steps, warmup, chunk, n_reps=None, groups=0
             out["autotune_s"] = round(tuned, 2)
             out["tuned"] = {"groups": ctx.get_groups() if form == "batched" else 1, "grid": ctx.get_grid(),
                             "taper": ctx.get_taper(), "tiles": sorted({ctx.get_tile(i) for i in range(len(reps))})}
+            if form == "persistent":
+                out["tuned"]["barriers"] = "team" if ctx.get_barriers() == islf.BARRIER_TEAM else "grid"
         out["ctx_means"] = ctx.means(done - steps, steps)
         return out
     finally:
@@ -311,6 +315,9 @@ def config_figures(islf, torch, steps, warmup, chunk, serve_requests, serve_budg
             h = np.arange(64) / 63.0
             cum = islf.integrate(h, m[:, 3], m[:, 4], -1.0, 1.0, 1.0 / (120 * 120))
             ti["delta_f1_at_h1_1"] = float(cum[-1])
+    r = run_form(islf, torch, "persistent", "bitpack", st, wu, min(chunk, 50), reps=ti_replicas(islf),
+                 min_warm_s=0.2, barriers=islf.BARRIER_TEAM)
+    ti["persistent_bitpack_team_barriers"] = round(rate(r), 2)
     for form in ("batched", "persistent"):
         r = run_form(islf, torch, form, "bitpack", st, wu, min(chunk, 50), reps=ti_replicas(islf), autotune=4,
                      min_warm_s=0.2)
@@ -479,6 +486,10 @@ def main():
                          min_warm_s=0.2)
             forms[f"{form}_{fmt}"] = round(rate(r), 2)
             print(f"# {form}/{fmt}: {brief(r)}", file=sys.stderr, flush=True)
+        r = run_form(islf, torch, "persistent", "bitpack", min(args.steps, 100), min(args.warmup, 50),
+                     min(args.chunk, 50), min_warm_s=0.2, barriers=islf.BARRIER_TEAM)
+        forms["persistent_bitpack_team_barriers"] = round(rate(r), 2)
+        print(f"# persistent/bitpack team barriers: {brief(r)}", file=sys.stderr, flush=True)
         # a batch larger than the 256 MB last-level cache: 8 int8 replicas, 369 MB of spins
         r = run_form(islf, torch, "batched", "int8", min(args.steps, 50), min(args.warmup, 50), min(args.chunk, 50),
                      n_reps=8, min_warm_s=0.2)

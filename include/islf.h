@@ -298,9 +298,10 @@ islf_status islf_run_graph(islf_ctx *ctx, uint32_t n_replays);
  * fastest kept; (2) for the context's execution form, the launch
  * configuration on the whole batch: batched, concurrent groups 1..4 x
  * workgroups per launch (1/2, 1, 3/2 of the default) x share taper
- * (0, 0.1, 0.2); persistent, grids of up to one workgroup per CU below the
- * co-residency bound x the same tapers; the fastest is kept (islf_get_groups,
- * islf_get_grid, islf_get_taper report it).  Spins, records and sweep
+ * (0, 0.1, 0.2); persistent, grid or team barriers x grids of up to one
+ * workgroup per CU below the co-residency bound x the same tapers; the
+ * fastest is kept (islf_get_groups, islf_get_grid, islf_get_taper,
+ * islf_get_barriers report it).  Spins, records and sweep
  * counters are restored afterwards, so results are unaffected.  Synchronises.
  * Errors: EINVAL, ENOMEM (backups), EDEVICE. */
 islf_status islf_num_tiles(int32_t spin_format, int32_t *n);
@@ -391,6 +392,21 @@ islf_status islf_get_grid(const islf_ctx *ctx, int32_t *workgroups);
  * The sweeps are real (they advance the chains).  Synchronises.
  * Errors: EINVAL, EDEVICE, ERANGE. */
 islf_status islf_phase_timings(islf_ctx *ctx, uint32_t n_sweeps, double *mean_ms, uint32_t *launches);
+
+/* Barriers of the persistent form.  ISLF_BARRIER_GRID (the default): one
+ * plan over all replicas and grid-wide barriers.  ISLF_BARRIER_TEAM: the
+ * cooperative grid is dealt to the live replicas (one workgroup each, then
+ * greedily to the replica with the most sites per workgroup), each
+ * replica's work is split over its team of workgroups, and a team meets at a
+ * barrier of its own between the launch stages, so replicas never wait for
+ * each other (used when every live replica can have at least one workgroup,
+ * else the grid form).  islf_autotune tries both.  Both compute the same
+ * result.
+ * islf_get_barriers reports the form the next persistent launch uses.
+ * Changing it invalidates a captured graph.  Errors: EINVAL. */
+typedef enum { ISLF_BARRIER_GRID = 0, ISLF_BARRIER_TEAM = 1 } islf_barrier_mode;
+islf_status islf_set_barriers(islf_ctx *ctx, int32_t mode);
+islf_status islf_get_barriers(const islf_ctx *ctx, int32_t *mode);
 
 /* Thread-local message describing the last failure on this thread. */
 const char *islf_last_error(void);

@@ -25,8 +25,12 @@ hipError_t sweep_blocks_per_cu(int fmt, int *per_cu);
 hipError_t launch_fold(const RepDesc *descs, RepState *st, const int *reps, int n_reps, uint32_t s,
                        uint32_t advance, hipStream_t strm);
 const void *persistent_kernel(int fmt);
+const void *persistent_teams_kernel(int fmt);
 hipError_t launch_persistent(int fmt, const RepDesc *descs, RepState *st, const Entry *items, const int *first,
                              const int *reps, int nreps, uint32_t nsweeps, GridSync *sync, int grid, hipStream_t s);
+hipError_t launch_persistent_teams(int fmt, const RepDesc *descs, RepState *st, const Entry *items, const int *first,
+                                   const TeamInfo *teams, uint32_t nsweeps, GridSync *sync, SyncLine *rsync,
+                                   int n_rsync, int grid, hipStream_t s);
 hipError_t launch_init(int fmt, const RepDesc *descs, int rep, int mode, const int8_t *host, hipStream_t s);
 hipError_t launch_export(const RepDesc *descs, int rep, long rows, int8_t *out, hipStream_t s);
 hipError_t launch_recompute(const RepDesc *descs, int rep, long rows, const int8_t *spins, unsigned long long *out,
@@ -237,6 +241,14 @@ struct islf_ctx {
     RepDesc *d_desc = nullptr;
     RepState *d_state = nullptr;
     GridSync *d_sync = nullptr;
+    // team form of the persistent plan: per-workgroup team records and one
+    // arrival counter per replica slot
+    bool persistent_teams = false;
+    TeamInfo *d_teams = nullptr;
+    long teams_cap = 0;
+    SyncLine *d_rsync = nullptr;
+    int rsync_cap = 0;
+    int team_mode = 0;         // 1: team barriers when every live replica can have a workgroup; 0: grid barriers
     unsigned long long *d_scratch = nullptr;   // 64 x u64
     int *d_live = nullptr;                      // live replica ids
     int live_capacity = 0;
@@ -558,12 +570,19 @@ static int partition_items(const std::vector<Entry> &slab, const std::vector<Ent
     return (int)gs;
 }
 
+static islf_status upload_plan(islf_ctx *c, Plan &p, const std::vector<Entry> &items, const std::vector<int> &first);
+
 static islf_status build_plan(islf_ctx *c, Plan &p, const std::vector<Entry> &slab, const std::vector<Entry> &main,
                               int grid, double taper = -1.0)
 {
     std::vector<Entry> items;
     std::vector<int> first;
     p.slab_grid = partition_items(slab, main, grid, items, first, taper < 0.0 ? tail_taper(c->fmt) : taper);
+    return upload_plan(c, p, items, first);
+}
+
+static islf_status upload_plan(islf_ctx *c, Plan &p, const std::vector<Entry> &items, const std::vector<int> &first)
+{
     p.grid = (int)first.size() - 1;
     if ((long)items.size() > p.items_cap) {
         dev_free(c, p.items);
@@ -701,6 +720,69 @@ static islf_status prepare_groups(islf_ctx *c)
     return ISLF_OK;
 }
 
+// The team form of the persistent plan: the grid's workgroups are dealt to
+// the live replicas so that the largest number of sites per workgroup is as
+// small as it can be (one each, then greedily), each replica's items are cut
+// into equal-cost runs over its team, and the teams take contiguous plan
+// slots (so a team's workgroups share an XCD where the team is small enough).
+static islf_status build_team_plan(islf_ctx *c, int grid, double taper)
+{
+    const int nl = (int)c->live.size();
+    std::vector<long long> sites(nl);
+    long long total = 0;
+    for (int i = 0; i < nl; ++i) {
+        const islf_replica_desc &d = c->reps[c->live[i]].desc;
+        sites[i] = (long long)d.Lx * d.Ly * d.Lz;
+        total += sites[i];
+    }
+    // one workgroup each, then each further workgroup to the team with the
+    // most sites per workgroup: the slowest team sets the launch's time
+    std::vector<int> W(nl, 1);
+    std::vector<std::pair<double, int>> heap;
+    for (int i = 0; i < nl; ++i) heap.push_back({(double)sites[i], i});
+    std::make_heap(heap.begin(), heap.end());
+    for (int used = nl; used < grid; ++used) {
+        std::pop_heap(heap.begin(), heap.end());
+        const int i = heap.back().second;
+        W[i] += 1;
+        heap.back().first = (double)sites[i] / (double)W[i];
+        std::push_heap(heap.begin(), heap.end());
+    }
+    (void)total;
+    std::vector<Entry> items;
+    std::vector<int> first(1, 0);
+    std::vector<TeamInfo> teams;
+    for (int i = 0; i < nl; ++i) {
+        const int r = c->live[i];
+        std::vector<Entry> it;
+        std::vector<int> fi;
+        partition_items(c->reps[r].slab, c->reps[r].main, W[i], it, fi, taper);
+        const int n = (int)fi.size() - 1;
+        const int off = (int)items.size();
+        items.insert(items.end(), it.begin(), it.end());
+        for (int b = 0; b < n; ++b) {
+            first.push_back(off + fi[b + 1]);
+            teams.push_back(TeamInfo{r, b, n, 0});
+        }
+    }
+    if ((long)teams.size() > c->teams_cap) {
+        dev_free(c, c->d_teams);
+        c->teams_cap = std::max<long>((long)teams.size(), 2 * c->teams_cap);
+        c->d_teams = (TeamInfo *)dev_alloc(c, sizeof(TeamInfo) * c->teams_cap);
+        if (!c->d_teams) return fail(ISLF_ENOMEM, "cannot allocate team records");
+    }
+    if (c->slot_capacity > c->rsync_cap) {
+        dev_free(c, c->d_rsync);
+        c->rsync_cap = c->slot_capacity;
+        c->d_rsync = (SyncLine *)dev_alloc(c, 2 * sizeof(SyncLine) * c->rsync_cap);
+        if (!c->d_rsync) return fail(ISLF_ENOMEM, "cannot allocate team counters");
+    }
+    HIP_TRY(hipMemcpyAsync(c->d_teams, teams.data(), sizeof(TeamInfo) * teams.size(), hipMemcpyHostToDevice,
+                           c->stream));
+    c->persistent_teams = true;
+    return upload_plan(c, c->persistent, items, first);
+}
+
 static islf_status prepare_plans(islf_ctx *c, int exec)
 {
     islf_status st = sync_tables(c);
@@ -726,8 +808,10 @@ static islf_status prepare_plans(islf_ctx *c, int exec)
         if (grid > c->persistent_bound)
             return fail(ISLF_ERANGE, "persistent grid %d exceeds the co-residency bound %d of this device", grid,
                         c->persistent_bound);
-        return build_plan(c, c->persistent, S, M, grid,
-                          c->taper_override >= 0.0 ? c->taper_override : kPersistentTaper);
+        const double taper = c->taper_override >= 0.0 ? c->taper_override : kPersistentTaper;
+        if (c->team_mode && (int)c->live.size() <= grid) return build_team_plan(c, grid, taper);
+        c->persistent_teams = false;
+        return build_plan(c, c->persistent, S, M, grid, taper);
     }
     if (exec == ISLF_EXEC_PLAIN) {
         if (c->plain.size() < c->reps.size()) c->plain.resize(c->reps.size());
@@ -821,6 +905,8 @@ static void destroy_ctx(islf_ctx *c)
     dev_free(c, c->d_desc);
     dev_free(c, c->d_state);
     dev_free(c, c->d_sync);
+    dev_free(c, c->d_teams);
+    dev_free(c, c->d_rsync);
     dev_free(c, c->d_scratch);
     dev_free(c, c->d_live);
     free_plan(c, c->batched);
@@ -892,7 +978,10 @@ extern "C" islf_status islf_create_with_allocator(const islf_replica_desc *reps,
     // round leaves slots idle while the last workgroups finish)
     c->resident_slots = c->num_cu * per_cu_sweep;
     c->sweep_slots = 2 * c->resident_slots;
-    const int per_cu = coresident_per_cu(persistent_kernel(spin_format), prop);
+    // both forms of the persistent kernel (grid and team barriers) launch on
+    // the same grid: the bound is the smaller of the two
+    const int per_cu = std::min(coresident_per_cu(persistent_kernel(spin_format), prop),
+                                coresident_per_cu(persistent_teams_kernel(spin_format), prop));
     c->persistent_bound = std::min(c->num_cu * per_cu, kBarrierGroup * kMaxGroups);
     // one slot per CU stays free by default: at the full occupancy the
     // runtime reported for an earlier build of the int8 kernel (7 workgroups
@@ -1108,8 +1197,11 @@ static islf_status enqueue_sweeps(islf_ctx *c, uint32_t n)
     if (nl == 0 || n == 0) return ISLF_OK;
     if (c->exec == ISLF_EXEC_PERSISTENT) {
         const Plan &p = c->persistent;
-        hipError_t e = launch_persistent(c->fmt, c->d_desc, c->d_state, p.items, p.first, c->d_live, nl, n,
-                                         c->d_sync, p.grid, c->stream);
+        hipError_t e = c->persistent_teams
+                           ? launch_persistent_teams(c->fmt, c->d_desc, c->d_state, p.items, p.first, c->d_teams, n,
+                                                     c->d_sync, c->d_rsync, c->rsync_cap, p.grid, c->stream)
+                           : launch_persistent(c->fmt, c->d_desc, c->d_state, p.items, p.first, c->d_live, nl, n,
+                                               c->d_sync, p.grid, c->stream);
         if (e != hipSuccess) return fail(ISLF_EDEVICE, "persistent launch failed: %s", hipGetErrorString(e));
         return ISLF_OK;
     }
@@ -1743,7 +1835,8 @@ extern "C" islf_status islf_autotune(islf_ctx *ctx, uint32_t sweeps)
         result = sync_tables(ctx);
         const int keep_groups = ctx->groups_req, keep_grid = ctx->grid_override;
         const double keep_taper = ctx->taper_override;
-        struct Trial { int groups, grid; double taper; };
+        struct Trial { int groups, grid; double taper; int team; };
+        const int keep_team = ctx->team_mode;
         std::vector<Trial> trials;
         const double tapers[] = {0.0, 0.1, 0.2};
         if (ctx->exec == ISLF_EXEC_BATCHED) {
@@ -1751,26 +1844,28 @@ extern "C" islf_status islf_autotune(islf_ctx *ctx, uint32_t sweeps)
             for (int G = 1; G <= std::min(4, nl); ++G) {
                 const int base = G == 1 ? ctx->sweep_slots : std::max(64, (3 * ctx->resident_slots + G) / (2 * G));
                 for (double f : {0.5, 1.0, 1.5})
-                    for (double tp : tapers) trials.push_back(Trial{G, std::max(32, (int)(base * f + 0.5)), tp});
+                    for (double tp : tapers) trials.push_back(Trial{G, std::max(32, (int)(base * f + 0.5)), tp, keep_team});
             }
         } else {
             // up to one workgroup per CU below the bound, like the default grid
             const int per_cu = std::max(1, ctx->persistent_bound / std::max(1, ctx->num_cu));
             const int top = std::max(1, per_cu - 1);
-            for (int k = std::max(1, top - 2); k <= top; ++k)
-                for (double tp : tapers)
-                    trials.push_back(Trial{0, std::min(ctx->num_cu * k, ctx->persistent_bound), tp});
+            for (int team = 0; team <= 1; ++team)
+                for (int k = std::max(1, top - 2); k <= top; ++k)
+                    for (double tp : tapers)
+                        trials.push_back(Trial{0, std::min(ctx->num_cu * k, ctx->persistent_bound), tp, team});
         }
         hipEvent_t e0 = nullptr, e1 = nullptr;
         if (result == ISLF_OK && (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess))
             result = fail(ISLF_EDEVICE, "cannot create events");
         double best = 1e300;
-        Trial best_t{keep_groups, keep_grid, keep_taper};
+        Trial best_t{keep_groups, keep_grid, keep_taper, keep_team};
         for (const Trial &t : trials) {
             if (result != ISLF_OK) break;
             ctx->groups_req = t.groups ? t.groups : keep_groups;
             ctx->grid_override = t.grid;
             ctx->taper_override = t.taper;
+            ctx->team_mode = t.team;
             ctx->groups_valid = false;
             ctx->batched.valid = false;
             ctx->persistent.valid = false;
@@ -1818,6 +1913,7 @@ extern "C" islf_status islf_autotune(islf_ctx *ctx, uint32_t sweeps)
         ctx->groups_req = (result == ISLF_OK && best_t.groups) ? best_t.groups : keep_groups;
         ctx->grid_override = result == ISLF_OK ? best_t.grid : keep_grid;
         ctx->taper_override = result == ISLF_OK ? best_t.taper : keep_taper;
+        ctx->team_mode = result == ISLF_OK ? best_t.team : keep_team;
         ctx->groups_valid = false;
         ctx->batched.valid = false;
         ctx->persistent.valid = false;
@@ -2028,5 +2124,25 @@ extern "C" islf_status islf_get_taper(const islf_ctx *ctx, double *taper)
     if (!ctx || !taper) return fail(ISLF_EINVAL, "NULL argument");
     if (ctx->taper_override >= 0.0) *taper = ctx->taper_override;
     else *taper = ctx->exec == ISLF_EXEC_PERSISTENT ? kPersistentTaper : tail_taper(ctx->fmt);
+    return ISLF_OK;
+}
+
+extern "C" islf_status islf_set_barriers(islf_ctx *ctx, int32_t mode)
+{
+    if (!ctx) return fail(ISLF_EINVAL, "NULL context");
+    if (mode != ISLF_BARRIER_GRID && mode != ISLF_BARRIER_TEAM) return fail(ISLF_EINVAL, "invalid barrier mode %d", mode);
+    ctx->team_mode = mode == ISLF_BARRIER_TEAM ? 1 : 0;
+    ctx->persistent.valid = false;
+    ctx->graph_valid = false;
+    return ISLF_OK;
+}
+
+extern "C" islf_status islf_get_barriers(const islf_ctx *ctx, int32_t *mode)
+{
+    if (!ctx || !mode) return fail(ISLF_EINVAL, "NULL argument");
+    // the mode the next persistent launch uses: team barriers need a
+    // workgroup for every live replica
+    const int grid = ctx->grid_override ? ctx->grid_override : ctx->persistent_grid;
+    *mode = ctx->team_mode && (int)ctx->live.size() <= grid ? ISLF_BARRIER_TEAM : ISLF_BARRIER_GRID;
     return ISLF_OK;
 }

@@ -93,4 +93,15 @@ struct GridSync {
     SyncLine release[kMaxGroups];
 };
 
+// Team form of the persistent kernel: every workgroup serves one replica
+// (its team), and a team's workgroups meet at a barrier of their own (an
+// arrival and a release counter per replica slot, each on its own line,
+// re-zeroed before each launch), so replicas do not wait for each other.
+struct TeamInfo {
+    int32_t rep;    // replica slot
+    int32_t rank;   // 0 .. size-1 inside the team (rank 0 folds the records)
+    int32_t size;   // workgroups of the team
+    int32_t pad_;
+};
+
 }  // namespace islf

@@ -1153,6 +1153,69 @@ __global__ __launch_bounds__(kBlock, 4) void k_persistent(const RepDesc *__restr
     fold_waves<true>(descs, st, reps, n_reps, n_sweeps - 1, n_sweeps);
 }
 
+// Barrier of one team (the workgroups of one replica): an arrival counter
+// and a release counter on lines of their own; the last of the `size`
+// members to arrive for barrier k bumps the release counter, which the
+// members poll (the polls never touch the line the arrivals update).  The
+// same ordering argument as grid_barrier (device-coherent accesses, every
+// wave's memory operations complete before its workgroup arrives).
+__device__ bool team_barrier(GridSync *sync, SyncLine *team, unsigned long long size, unsigned long long &passed)
+{
+    __builtin_amdgcn_s_waitcnt(0);
+    __syncthreads();
+    __shared__ int ok;
+    if (threadIdx.x == 0) {
+        const unsigned long long k1 = passed + 1;
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+        const unsigned long long old = atomicAdd(&team[0].v, 1ull);
+        if (old + 1 == k1 * size) atomicAdd(&team[1].v, 1ull);
+        const bool good = sync_wait(sync, &team[1].v, k1);
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+        ok = good ? 1 : 0;
+    }
+    passed += 1;
+    __syncthreads();
+    return ok != 0;
+}
+
+// The persistent schedule with team barriers: workgroup b runs its items
+// (all of one replica) through the A / B launches of every sweep, meeting
+// its team between them; rank 0 of a team folds its replica's records and,
+// at the end, advances its sweep counter.  A barrier that gives up (bounded
+// wait, or a raised error word) ends every workgroup at its next barrier.
+template <int FMT>
+__global__ __launch_bounds__(kBlock, 4) void k_persistent_teams(const RepDesc *__restrict__ descs,
+                                                                RepState *__restrict__ st,
+                                                                const Entry *__restrict__ items,
+                                                                const int *__restrict__ first,
+                                                                const TeamInfo *__restrict__ teams,
+                                                                uint32_t n_sweeps, GridSync *sync,
+                                                                SyncLine *rsync)
+{
+    __shared__ Tables tb;
+    const int b = plan_block();
+    const TeamInfo ti = teams[b];
+    const int i0 = first[b], i1 = first[b + 1];
+    SyncLine *ctr = rsync + 2 * ti.rep;   // arrival, release
+    const unsigned long long size = (unsigned long long)ti.size;
+    const bool folder = ti.rank == 0 && threadIdx.x < 64;   // wave 0 of rank 0
+    const int lane = threadIdx.x & 63;
+    unsigned long long passed = 0;
+    for (uint32_t s = 0; s < n_sweeps; ++s) {
+        run_items<FMT, KIND_A, true>(descs, st, items, i0, i1, s, s ? FLAG_PREV : 0u, &tb);
+        if (!team_barrier(sync, ctr, size, passed)) return;
+        if (s > 0 && folder) fold_sweep<true>(descs[ti.rep], st[ti.rep], st[ti.rep].t + s - 1, lane);
+        run_items<FMT, KIND_B, true>(descs, st, items, i0, i1, s, 0u, &tb);
+        if (!team_barrier(sync, ctr, size, passed)) return;
+    }
+    run_items<FMT, KIND_F, true>(descs, st, items, i0, i1, n_sweeps - 1, 0u, &tb);
+    if (!team_barrier(sync, ctr, size, passed)) return;
+    if (folder) {
+        fold_sweep<true>(descs[ti.rep], st[ti.rep], st[ti.rep].t + n_sweeps - 1, lane);
+        if (lane == 0) st[ti.rep].t += n_sweeps;
+    }
+}
+
 // ---------------------------------------------------------------------------
 // Initial states and format conversion.
 // mode 0: random (Philox domain 1, t = 0; +1 iff the word's top bit is 0),
@@ -1568,6 +1631,26 @@ hipError_t launch_persistent(int fmt, const RepDesc *descs, RepState *st, const 
     const hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     return hipLaunchCooperativeKernel(persistent_kernel(fmt), dim3(grid), dim3(kBlock), args, 0, s);
+}
+
+const void *persistent_teams_kernel(int fmt)
+{
+    return fmt == ISLF_SPIN_INT8 ? (const void *)k_persistent_teams<ISLF_SPIN_INT8>
+                                 : (const void *)k_persistent_teams<ISLF_SPIN_BITPACK>;
+}
+
+hipError_t launch_persistent_teams(int fmt, const RepDesc *descs, RepState *st, const Entry *items, const int *first,
+                                   const TeamInfo *teams, uint32_t nsweeps, GridSync *sync, SyncLine *rsync,
+                                   int n_rsync, int grid, hipStream_t s)
+{
+    void *args[] = {(void *)&descs, (void *)&st, (void *)&items, (void *)&first,
+                    (void *)&teams, (void *)&nsweeps, (void *)&sync, (void *)&rsync};
+    // fresh team counters for this launch (the error line is kept): two
+    // lines per replica slot
+    hipLaunchKernelGGL(k_zero_u64, dim3(64), dim3(256), 0, s, (unsigned long long *)rsync, (long)n_rsync * 2 * 16);
+    const hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    return hipLaunchCooperativeKernel(persistent_teams_kernel(fmt), dim3(grid), dim3(kBlock), args, 0, s);
 }
 
 hipError_t launch_init(int fmt, const RepDesc *descs, int rep, int mode, const int8_t *host, hipStream_t s)

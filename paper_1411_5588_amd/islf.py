@@ -27,6 +27,7 @@ PBC, APBC, GAPBC = 0, 1, 2
 INT8, BITPACK = 0, 1
 INIT_RANDOM, INIT_UP, INIT_DOWN, INIT_HOST = 0, 1, 2, 3
 EXEC_PLAIN, EXEC_BATCHED, EXEC_PERSISTENT = 0, 1, 2
+BARRIER_GRID, BARRIER_TEAM = 0, 1
 
 _STATUS = {EINVAL: "EINVAL", ENOMEM: "ENOMEM", EDEVICE: "EDEVICE", ESTATE: "ESTATE", ERANGE: "ERANGE"}
 
@@ -126,6 +127,8 @@ def lib():
             "islf_replica_means": [vp, i32, u64, u32, vp],
             "islf_device_bytes": [vp, P(u64), P(u64)],
             "islf_set_taper": [vp, dbl],
+            "islf_set_barriers": [vp, i32],
+            "islf_get_barriers": [vp, P(i32)],
             "islf_get_taper": [vp, P(dbl)],
             "islf_testing_raise_barrier_error": [vp],
         }
@@ -387,6 +390,15 @@ class Context:
         t, r = C.c_uint64(), C.c_uint64()
         _check(lib().islf_device_bytes(self._h, C.byref(t), C.byref(r)))
         return t.value, r.value
+
+    def set_barriers(self, mode: int):
+        """Barriers of the persistent form: BARRIER_TEAM (per replica) or BARRIER_GRID."""
+        _check(lib().islf_set_barriers(self._h, mode))
+
+    def get_barriers(self) -> int:
+        m = C.c_int32()
+        _check(lib().islf_get_barriers(self._h, C.byref(m)))
+        return m.value
 
     def set_taper(self, taper: float):
         """Share taper of the batched and persistent plans (< 0: built-in)."""

@@ -185,3 +185,30 @@ def test_phase_timings_are_real_sweeps():
     for i, p in enumerate(ps):
         _, o_rec, _ = oracle_trajectory(p, 5)
         assert np.array_equal(recs[i], o_rec)
+
+
+@pytest.mark.parametrize("fmt", [islf.INT8, islf.BITPACK])
+@pytest.mark.parametrize("barriers", [islf.BARRIER_TEAM, islf.BARRIER_GRID])
+def test_persistent_barrier_forms(fmt, barriers):
+    # team barriers (each replica's workgroups meet on their own) and grid
+    # barriers give the same chains, eager and under graph replay; a grid
+    # smaller than the replica count falls back to grid barriers
+    ps = batch_params()
+    with islf.Context([islf.Replica(**p) for p in ps], spin_format=fmt, obs_capacity=64,
+                      exec_mode=islf.EXEC_PERSISTENT) as ctx:
+        ctx.set_barriers(barriers)
+        assert ctx.get_barriers() == barriers
+        ctx.sweep(3)
+        ctx.capture(4)
+        ctx.replay(2)
+        ctx.set_grid(3)                     # fewer workgroups than replicas
+        assert ctx.get_barriers() == islf.BARRIER_GRID
+        ctx.sweep(2)
+        ctx.set_grid(0)
+        ctx.sweep(1)
+        recs = [ctx.measure(i, 0, 14) for i in range(len(ps))]
+        spins = [ctx.get_spins(i) for i in range(len(ps))]
+    for i, p in enumerate(ps):
+        _, o_rec, o_s = oracle_trajectory(p, 14)
+        assert np.array_equal(recs[i], o_rec), i
+        assert np.array_equal(spins[i], o_s), i

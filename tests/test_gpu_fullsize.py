@@ -52,21 +52,24 @@ def oracle_all():
     yield ths, out
 
 
-@pytest.mark.parametrize("fmt,exec_mode,graph", [(islf.INT8, islf.EXEC_BATCHED, False),
-                                                 (islf.INT8, islf.EXEC_BATCHED, True),
-                                                 (islf.BITPACK, islf.EXEC_BATCHED, False),
-                                                 (islf.BITPACK, islf.EXEC_BATCHED, True),
-                                                 (islf.INT8, islf.EXEC_PERSISTENT, True),
-                                                 (islf.BITPACK, islf.EXEC_PERSISTENT, True),
-                                                 (islf.INT8, islf.EXEC_PLAIN, False),
-                                                 (islf.BITPACK, islf.EXEC_PLAIN, True)])
-def test_paper_scale_two_sweeps_bit_exact(oracle_all, fmt, exec_mode, graph):
+@pytest.mark.parametrize("fmt,exec_mode,graph,barriers", [(islf.INT8, islf.EXEC_BATCHED, False, None),
+                                                          (islf.INT8, islf.EXEC_BATCHED, True, None),
+                                                          (islf.BITPACK, islf.EXEC_BATCHED, False, None),
+                                                          (islf.BITPACK, islf.EXEC_BATCHED, True, None),
+                                                          (islf.INT8, islf.EXEC_PERSISTENT, True, islf.BARRIER_TEAM),
+                                                          (islf.BITPACK, islf.EXEC_PERSISTENT, True, islf.BARRIER_TEAM),
+                                                          (islf.BITPACK, islf.EXEC_PERSISTENT, True, islf.BARRIER_GRID),
+                                                          (islf.INT8, islf.EXEC_PLAIN, False, None),
+                                                          (islf.BITPACK, islf.EXEC_PLAIN, True, None)])
+def test_paper_scale_two_sweeps_bit_exact(oracle_all, fmt, exec_mode, graph, barriers):
     ths, out = oracle_all
     # the batch the benchmark runs: T = 2, 3, 4 side by side, in its default
     # launch configuration (concurrent replica groups); graph: captured and
     # replayed as the benchmark does.  Every replica is compared.
     reps = [islf.Replica(**params(T, i)) for i, T in enumerate(TEMPS)]
     with islf.Context(reps, spin_format=fmt, obs_capacity=16, exec_mode=exec_mode) as ctx:
+        if barriers is not None:
+            ctx.set_barriers(barriers)
         s0 = [ctx.get_spins(i) for i in range(3)]
         if graph:
             ctx.capture(2)
