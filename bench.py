@@ -68,6 +68,8 @@ def parse():
                     help="workgroups per launch of the headline form (0: the library's default)")
     ap.add_argument("--tile", type=int, default=-1,
                     help="tile variant of every replica of the headline form (-1: the library's default)")
+    ap.add_argument("--taper", type=float, default=None, help="share taper of the headline form's plans")
+    ap.add_argument("--barriers", choices=["grid", "team"], default=None, help="barriers of the persistent form")
     ap.add_argument("--form", choices=["persistent", "batched", "plain"], default="batched")
     ap.add_argument("--fmt", choices=["int8", "bitpack"], default="bitpack")
     ap.add_argument("--no-extras", action="store_true", help="skip the other forms and formats")
@@ -96,7 +98,7 @@ def replicas(islf, n=None):
 
 
 def run_form(islf, torch, form, fmt, steps, warmup, chunk, n_reps=None, groups=0, reps=None, autotune=0, grid=0,
-             tile=-1, min_warm_s=0.5, barriers=None):
+             tile=-1, min_warm_s=0.5, barriers=None, taper=None):
     """Times `steps` sweeps of a batch in one execution form: graph replays of
     `chunk` sweeps (plus eager sweeps for a remainder), after the warm-up:
     at least `warmup` sweeps, at least one untimed replay of the same graph,
@@ -115,6 +117,8 @@ def run_form(islf, torch, form, fmt, steps, warmup, chunk, n_reps=None, groups=0
         tuned = 0.0
         if barriers is not None:
             ctx.set_barriers(barriers)
+        if taper is not None:
+            ctx.set_taper(taper)
         if autotune:
             t = time.perf_counter()
             ctx.autotune(autotune)
@@ -461,8 +465,9 @@ def main():
         return {k: v for k, v in r.items() if k != "ctx_means"}
 
     WARM_S = args.min_warmup_s
+    bars = None if args.barriers is None else (islf.BARRIER_TEAM if args.barriers == "team" else islf.BARRIER_GRID)
     main_run = run_form(islf, torch, args.form, args.fmt, args.steps, args.warmup, args.chunk, groups=args.groups,
-                        grid=args.grid, tile=args.tile, min_warm_s=WARM_S)
+                        grid=args.grid, tile=args.tile, min_warm_s=WARM_S, barriers=bars, taper=args.taper)
     print(f"# {args.form}/{args.fmt}: {brief(main_run)}", file=sys.stderr, flush=True)
     value = rate(main_run)
     # the same form as one launch chain over all replicas, timed the same way:
@@ -507,26 +512,40 @@ def main():
     # a sweep of every replica; the one-chain timed region over its 2 x steps
     # launches is the average launch duration (the region also holds one
     # closing launch and fold per graph launch, so this slightly overstates it)
-    bpu = BYTES_PER_UPDATE[args.fmt]
-    updates_per_launch = n_reps * N / 2
-    alg_bytes = bpu * updates_per_launch
-    launch_ms = chain_run["ms_per_sweep"] / 2
-    achieved = alg_bytes / (launch_ms * 1e-3) / 1e9
-    wave_ms = main_run["ms_per_sweep"] / 2
-    wave_gbs = alg_bytes / (wave_ms * 1e-3) / 1e9
-    roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": committed_traffic(args.fmt),
-                "kernel": "k_sweep (A and B launches), one launch over all three replicas",
-                "launch_ms": round(launch_ms, 5), "workgroups": chain_run["grid"],
-                "algorithmic_bytes_per_launch": alg_bytes, "bytes_per_update": bpu,
-                "roofline_updates_per_ns": HBM_PEAK_GBS / bpu,
-                "grouped_wave": {"wave_ms": round(wave_ms, 5), "achieved": round(wave_gbs, 1),
-                                 "frac": round(wave_gbs / HBM_PEAK_GBS, 4),
-                                 "unit": f"wave of {main_run['groups']} concurrent group dispatches of "
-                                         f"{main_run['grid']} workgroups (the headline form), half a sweep of "
-                                         f"every replica"},
-                "valu": committed_valu(args.fmt),
-                "limiter": "VALU issue: Philox4x32-10 costs 5 64-bit products and 5 xors per update"}
+    def roofline_of(fmt, chain, grouped):
+        bpu = BYTES_PER_UPDATE[fmt]
+        alg_bytes = bpu * n_reps * N / 2
+        launch_ms = chain["ms_per_sweep"] / 2
+        achieved = alg_bytes / (launch_ms * 1e-3) / 1e9
+        out = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+               "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": committed_traffic(fmt),
+               "kernel": "k_sweep (A and B launches), one launch over all three replicas",
+               "launch_ms": round(launch_ms, 5), "workgroups": chain["grid"],
+               "algorithmic_bytes_per_launch": alg_bytes, "bytes_per_update": bpu,
+               "roofline_updates_per_ns": HBM_PEAK_GBS / bpu}
+        if grouped is not None:
+            wave_ms = grouped["ms_per_sweep"] / 2
+            gbs = alg_bytes / (wave_ms * 1e-3) / 1e9
+            out["grouped_wave"] = {"wave_ms": round(wave_ms, 5), "achieved": round(gbs, 1),
+                                   "frac": round(gbs / HBM_PEAK_GBS, 4),
+                                   "unit": f"wave of {grouped['groups']} concurrent group dispatches of "
+                                           f"{grouped['grid']} workgroups, half a sweep of every replica"}
+        out["valu"] = committed_valu(fmt)
+        out["limiter"] = "VALU issue: Philox4x32-10 costs 5 64-bit products and 5 xors per update"
+        return out
+
+    roofline = roofline_of(args.fmt, chain_run, main_run if args.form == "batched" else None)
+    roofline["grouped_wave_is_headline_form"] = args.form == "batched"
+    if not args.no_extras:
+        # the other spin format's sweep kernel, measured the same way
+        other = "int8" if args.fmt == "bitpack" else "bitpack"
+        oc = run_form(islf, torch, "batched", other, min(args.steps, 400), min(args.warmup, 100), args.chunk,
+                      groups=1, min_warm_s=0.2)
+        og = run_form(islf, torch, "batched", other, min(args.steps, 400), min(args.warmup, 100), args.chunk,
+                      min_warm_s=0.2)
+        roofline[f"other_format_{other}"] = roofline_of(other, oc, og)
+        roofline[f"other_format_{other}"]["updates_per_ns_batched"] = round(rate(og), 2)
+        print(f"# {other} one chain: {brief(oc)}; grouped: {brief(og)}", file=sys.stderr, flush=True)
 
     prof = hio = None
     if not args.no_aux:

@@ -808,8 +808,12 @@ static islf_status prepare_plans(islf_ctx *c, int exec)
         if (grid > c->persistent_bound)
             return fail(ISLF_ERANGE, "persistent grid %d exceeds the co-residency bound %d of this device", grid,
                         c->persistent_bound);
+        // the team plan's runs are cut per team, outside the kernel's dispatch
+        // order, so its default is no taper (0.1 measured 8% slower than 0
+        // on three 46M lattices)
+        if (c->team_mode && (int)c->live.size() <= grid)
+            return build_team_plan(c, grid, c->taper_override >= 0.0 ? c->taper_override : 0.0);
         const double taper = c->taper_override >= 0.0 ? c->taper_override : kPersistentTaper;
-        if (c->team_mode && (int)c->live.size() <= grid) return build_team_plan(c, grid, taper);
         c->persistent_teams = false;
         return build_plan(c, c->persistent, S, M, grid, taper);
     }
@@ -2123,7 +2127,8 @@ extern "C" islf_status islf_get_taper(const islf_ctx *ctx, double *taper)
 {
     if (!ctx || !taper) return fail(ISLF_EINVAL, "NULL argument");
     if (ctx->taper_override >= 0.0) *taper = ctx->taper_override;
-    else *taper = ctx->exec == ISLF_EXEC_PERSISTENT ? kPersistentTaper : tail_taper(ctx->fmt);
+    else if (ctx->exec == ISLF_EXEC_PERSISTENT) *taper = ctx->persistent_teams ? 0.0 : kPersistentTaper;
+    else *taper = tail_taper(ctx->fmt);
     return ISLF_OK;
 }
 
