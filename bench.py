@@ -323,7 +323,7 @@ def config_figures(islf, torch, steps, warmup, chunk, serve_requests, serve_budg
                  min_warm_s=0.2, barriers=islf.BARRIER_TEAM)
     ti["persistent_bitpack_team_barriers"] = round(rate(r), 2)
     for form in ("batched", "persistent"):
-        r = run_form(islf, torch, form, "bitpack", st, wu, min(chunk, 50), reps=ti_replicas(islf), autotune=4,
+        r = run_form(islf, torch, form, "bitpack", st, wu, min(chunk, 50), reps=ti_replicas(islf), autotune=10,
                      min_warm_s=0.2)
         ti[f"{form}_bitpack_autotuned"] = round(rate(r), 2)
         ti[f"{form}_bitpack_tuned"] = r.get("tuned")
@@ -334,7 +334,7 @@ def config_figures(islf, torch, steps, warmup, chunk, serve_requests, serve_budg
                       "(short chains: a throughput check, not a physics result)")
     out["ti_64x40x120x120"] = ti
     un = {}
-    r = run_form(islf, torch, "batched", "int8", st, wu, min(chunk, 50), reps=uneven_replicas(islf), autotune=4,
+    r = run_form(islf, torch, "batched", "int8", st, wu, min(chunk, 50), reps=uneven_replicas(islf), autotune=10,
                  min_warm_s=0.2)
     un["batched_int8_autotuned"] = round(rate(r), 2)
     un["autotune_s"] = r.get("autotune_s")
