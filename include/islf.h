@@ -292,16 +292,18 @@ islf_status islf_run_graph(islf_ctx *ctx, uint32_t n_replays);
  * a replica.  Every variant computes the same result; they differ only in
  * the thread-to-site mapping.  islf_set_tile changes one replica's variant
  * (rebuilding work lists).
- * islf_autotune tunes the live batch in two steps, each trial timed over
- * `sweeps` sweeps after one untimed sweep: (1) per size class, every tile
- * variant (the class's replicas alone, in a batched plan of their own), the
- * fastest kept; (2) for the context's execution form, the launch
- * configuration on the whole batch: batched, concurrent groups 1..4 x
- * workgroups per launch (1/2, 1, 3/2 of the default) x share taper
- * (0, 0.1, 0.2); persistent, grid or team barriers x grids of up to one
- * workgroup per CU below the co-residency bound x the same tapers; the
- * fastest is kept (islf_get_groups, islf_get_grid, islf_get_taper,
- * islf_get_barriers report it).  Spins, records and sweep
+ * islf_autotune tunes the live batch in two steps; a trial is the shortest
+ * of three timed runs of `sweeps` sweeps after one untimed run: (1) per size
+ * class, every tile variant (the class's replicas alone, in a batched plan of
+ * their own), the fastest kept if it beats the class's own variant by 1%;
+ * (2) for the context's execution form, the launch configuration on the
+ * whole batch: batched, concurrent groups 1..4 x workgroups per launch (1/2,
+ * 1, 3/2 of the default) x share taper (0, 0.1, 0.2); persistent, grid or
+ * team barriers x grids of up to one workgroup per CU below the co-residency
+ * bound x the same tapers.  The four fastest and the configuration in use
+ * are timed again (shortest of six runs); a finalist replaces the one in use
+ * only if it is 1% faster (islf_get_groups, islf_get_grid, islf_get_taper,
+ * islf_get_barriers report the result).  Spins, records and sweep
  * counters are restored afterwards, so results are unaffected.  Synchronises.
  * Errors: EINVAL, ENOMEM (backups), EDEVICE. */
 islf_status islf_num_tiles(int32_t spin_format, int32_t *n);
