@@ -83,6 +83,8 @@ def parse():
     ap.add_argument("--serve", type=int, default=0, metavar="N",
                     help="instead: the serving workload, N Poisson requests (20/s, log-uniform sizes)")
     ap.add_argument("--serve-budget-mib", type=int, default=256)
+    ap.add_argument("--full-configs", action="store_true",
+                    help="instead: every configuration at its full sweep count, one JSON line of rates")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of MIB MiB (traffic counter calibration)")
     return ap.parse_args()
@@ -300,6 +302,38 @@ def uneven_replicas(islf):
     return out
 
 
+def full_configs(islf, torch):
+    """Every configuration at its full sweep count (graph replays of 50
+    sweeps after 200 warm-up sweeps): the small film (1,000 sweeps), the
+    paper-scale batch in every form and format (2,000), the batched TI batch
+    (10^4) and the uneven batch (5,000), default and autotuned."""
+    out = {}
+
+    def run(name, *a, **k):
+        r = run_form(islf, torch, *a, **k)
+        out[name] = {"updates_per_ns": round(rate(r), 2), "ms_per_sweep": round(r["ms_per_sweep"], 6),
+                     "groups": r["groups"], "grid": r["grid"]}
+        if "tuned" in r:
+            out[name]["tuned"] = r["tuned"]
+        print("#", name, out[name], file=sys.stderr, flush=True)
+
+    small = [islf.Replica(12, 24, 24, islf.GAPBC, J=1.0, beta=1.0 / 3.0, H=0.0, h1=0.5, hn=-0.5, seed=SEED,
+                          replica=0, init=islf.INIT_RANDOM)]
+    for fmt in ("int8", "bitpack"):
+        run(f"film_12x24x24_plain_{fmt}", "plain", fmt, 1000, 50, 50, reps=small)
+    for form in ("batched", "plain", "persistent"):
+        for fmt in ("bitpack", "int8"):
+            run(f"paper_scale_{form}_{fmt}", form, fmt, 2000, 200, 50)
+    for fmt in ("bitpack", "int8"):
+        run(f"ti_64_batched_{fmt}", "batched", fmt, 10000, 200, 50, reps=ti_replicas(islf))
+        run(f"ti_64_batched_{fmt}_autotuned", "batched", fmt, 10000, 200, 50, reps=ti_replicas(islf), autotune=10)
+        run(f"ti_64_persistent_{fmt}_autotuned", "persistent", fmt, 10000, 200, 50, reps=ti_replicas(islf),
+            autotune=10)
+    run("uneven_96_batched_int8_autotuned", "batched", "int8", 5000, 200, 50, reps=uneven_replicas(islf), autotune=10)
+    run("uneven_96_batched_bitpack", "batched", "bitpack", 5000, 200, 50, reps=uneven_replicas(islf))
+    return out
+
+
 def config_figures(islf, torch, steps, warmup, chunk, serve_requests, serve_budget_mib):
     """The batched configurations beside the headline: updates/ns per form
     and format, the field-path integral of the TI batch, serving latency."""
@@ -439,6 +473,11 @@ def main():
         b.copy_(a)
         torch.cuda.synchronize()
         print(json.dumps({"calibration_copy_bytes": n}), flush=True)
+        return
+
+    if args.full_configs:
+        print(json.dumps({"metric": "spin updates/ns", "full_configs": full_configs(islf, torch),
+                          "data": "synthetic"}), flush=True)
         return
 
     if args.serve:
