@@ -395,18 +395,20 @@ islf_status islf_get_grid(const islf_ctx *ctx, int32_t *workgroups);
  * Errors: EINVAL, EDEVICE, ERANGE. */
 islf_status islf_phase_timings(islf_ctx *ctx, uint32_t n_sweeps, double *mean_ms, uint32_t *launches);
 
-/* Barriers of the persistent form.  ISLF_BARRIER_GRID (the default): one
- * plan over all replicas and grid-wide barriers.  ISLF_BARRIER_TEAM: the
+/* Barriers of the persistent form.  ISLF_BARRIER_GRID: one plan over all
+ * replicas and grid-wide barriers.  ISLF_BARRIER_TEAM: the
  * cooperative grid is dealt to the live replicas (one workgroup each, then
  * greedily to the replica with the most sites per workgroup), each
  * replica's work is split over its team of workgroups, and a team meets at a
  * barrier of its own between the launch stages, so replicas never wait for
  * each other (used when every live replica can have at least one workgroup,
- * else the grid form).  islf_autotune tries both.  Both compute the same
- * result.
- * islf_get_barriers reports the form the next persistent launch uses.
- * Changing it invalidates a captured graph.  Errors: EINVAL. */
-typedef enum { ISLF_BARRIER_GRID = 0, ISLF_BARRIER_TEAM = 1 } islf_barrier_mode;
+ * else the grid form).  ISLF_BARRIER_AUTO (the default): team barriers for
+ * int8 spins or batches of 8 or more replicas, grid barriers otherwise (the
+ * faster form on the batches measured).  islf_autotune tries both.  All
+ * compute the same result.
+ * islf_get_barriers reports the form the next persistent launch uses (GRID
+ * or TEAM).  Changing it invalidates a captured graph.  Errors: EINVAL. */
+typedef enum { ISLF_BARRIER_GRID = 0, ISLF_BARRIER_TEAM = 1, ISLF_BARRIER_AUTO = 2 } islf_barrier_mode;
 islf_status islf_set_barriers(islf_ctx *ctx, int32_t mode);
 islf_status islf_get_barriers(const islf_ctx *ctx, int32_t *mode);
 

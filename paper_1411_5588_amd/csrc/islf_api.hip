@@ -248,7 +248,7 @@ struct islf_ctx {
     long teams_cap = 0;
     SyncLine *d_rsync = nullptr;
     int rsync_cap = 0;
-    int team_mode = 0;         // 1: team barriers when every live replica can have a workgroup; 0: grid barriers
+    int team_mode = -1;        // 1: team barriers when every live replica can have a workgroup; 0: grid; -1: automatic
     unsigned long long *d_scratch = nullptr;   // 64 x u64
     int *d_live = nullptr;                      // live replica ids
     int live_capacity = 0;
@@ -501,10 +501,13 @@ constexpr int kMaxStreamGroups = 16;   // concurrent replica groups of the batch
 // those workgroups covers them all); main tiles follow in order and fill
 // every workgroup up to its share.  A main tile costs 4 units per x step and
 // may be cut between steps; a slab tile costs 6 units (1.5 steps) per task
-// per thread over its three row stages and is never cut.  Returns the number
-// of workgroups holding slab items.
+// per thread over its three row stages and is never cut.  The runs may be a
+// part of a larger launch: run r is then the launch's run p0 + r of
+// launch_grid, which sets its dispatch rank for the taper.  Returns the
+// number of workgroups holding slab items.
 static int partition_items(const std::vector<Entry> &slab, const std::vector<Entry> &main, int grid,
-                           std::vector<Entry> &items, std::vector<int> &first, double taper)
+                           std::vector<Entry> &items, std::vector<int> &first, double taper, int p0 = 0,
+                           int launch_grid = 0)
 {
     auto slab_cost = [](const Entry &e) -> long long {
         const long long tasks = 6ll * e.y0 * e.nsteps;
@@ -526,20 +529,22 @@ static int partition_items(const std::vector<Entry> &slab, const std::vector<Ent
     // d(r) (the inverse of the kernel's XCD-contiguous mapping); later ranks
     // get smaller shares, weight 1 + a (1 - 2 u) at u = (d + 0.5) / grid
     const double a = taper;
+    const long LG = launch_grid > 0 ? launch_grid : grid;
     std::vector<double> cum(grid + 1, 0.0);
-    const long q = grid / 8, r8 = grid % 8;
+    const long q = LG / 8, r8 = LG % 8;
     for (int r = 0; r < grid; ++r) {
         // the kernel gives XCD x (blocks x, x+8, ...) the runs from x*q + min(x, r8)
+        const long rg = std::min<long>(p0 + r, LG - 1);
         long x, k;
-        if (r < r8 * (q + 1)) {
-            x = r / (q + 1);
-            k = r % (q + 1);
+        if (rg < r8 * (q + 1)) {
+            x = rg / (q + 1);
+            k = rg % (q + 1);
         } else {
-            x = r8 + (r - r8 * (q + 1)) / q;
-            k = (r - r8 * (q + 1)) % q;
+            x = r8 + (rg - r8 * (q + 1)) / q;
+            k = (rg - r8 * (q + 1)) % q;
         }
         const long d = x + 8 * k;
-        const double u = (d + 0.5) / grid;
+        const double u = (d + 0.5) / LG;
         cum[r + 1] = cum[r] + 1.0 + a * (1.0 - 2.0 * u);
     }
     for (int b = 0; b < grid; ++b) {
@@ -756,7 +761,9 @@ static islf_status build_team_plan(islf_ctx *c, int grid, double taper)
         const int r = c->live[i];
         std::vector<Entry> it;
         std::vector<int> fi;
-        partition_items(c->reps[r].slab, c->reps[r].main, W[i], it, fi, taper);
+        // the team's runs are the launch's runs first.size()-1 onwards: their
+        // dispatch ranks in the launch set the taper
+        partition_items(c->reps[r].slab, c->reps[r].main, W[i], it, fi, taper, (int)first.size() - 1, grid);
         const int n = (int)fi.size() - 1;
         const int off = (int)items.size();
         items.insert(items.end(), it.begin(), it.end());
@@ -781,6 +788,20 @@ static islf_status build_team_plan(islf_ctx *c, int grid, double taper)
                            c->stream));
     c->persistent_teams = true;
     return upload_plan(c, c->persistent, items, first);
+}
+
+// Whether the persistent launch uses team barriers.  Automatic: teams for
+// int8 spins or batches of 8 or more replicas, grid barriers for a few
+// bit-packed replicas; measured (updates/ns, grid / team): 3 x 160x480x600
+// bit-packed 1,780 / 1,562, int8 1,100 / 1,167; 64 x 40x120x120
+// bit-packed 795 / 834, int8 646 / 779.  Teams need a workgroup for every
+// live replica.
+static bool use_teams(const islf_ctx *c, int grid)
+{
+    const int nl = (int)c->live.size();
+    if (nl > grid) return false;
+    if (c->team_mode >= 0) return c->team_mode == 1;
+    return c->fmt == ISLF_SPIN_INT8 || nl >= 8;
 }
 
 static islf_status prepare_plans(islf_ctx *c, int exec)
@@ -808,10 +829,10 @@ static islf_status prepare_plans(islf_ctx *c, int exec)
         if (grid > c->persistent_bound)
             return fail(ISLF_ERANGE, "persistent grid %d exceeds the co-residency bound %d of this device", grid,
                         c->persistent_bound);
-        // the team plan's runs are cut per team, outside the kernel's dispatch
-        // order, so its default is no taper (0.1 measured 8% slower than 0
-        // on three 46M lattices)
-        if (c->team_mode && (int)c->live.size() <= grid)
+        // team plans taper by their launch-wide dispatch ranks too; untapered
+        // was as fast as or faster than 0.1 .. 0.3 on three 46M lattices and
+        // the 64-replica TI batch (bit-packed 1,562 against 1,503 .. 1,521)
+        if (use_teams(c, grid))
             return build_team_plan(c, grid, c->taper_override >= 0.0 ? c->taper_override : 0.0);
         const double taper = c->taper_override >= 0.0 ? c->taper_override : kPersistentTaper;
         c->persistent_teams = false;
@@ -2167,7 +2188,8 @@ extern "C" islf_status islf_get_taper(const islf_ctx *ctx, double *taper)
 {
     if (!ctx || !taper) return fail(ISLF_EINVAL, "NULL argument");
     if (ctx->taper_override >= 0.0) *taper = ctx->taper_override;
-    else if (ctx->exec == ISLF_EXEC_PERSISTENT) *taper = ctx->persistent_teams ? 0.0 : kPersistentTaper;
+    else if (ctx->exec == ISLF_EXEC_PERSISTENT)
+        *taper = use_teams(ctx, ctx->grid_override ? ctx->grid_override : ctx->persistent_grid) ? 0.0 : kPersistentTaper;
     else *taper = tail_taper(ctx->fmt);
     return ISLF_OK;
 }
@@ -2175,8 +2197,9 @@ extern "C" islf_status islf_get_taper(const islf_ctx *ctx, double *taper)
 extern "C" islf_status islf_set_barriers(islf_ctx *ctx, int32_t mode)
 {
     if (!ctx) return fail(ISLF_EINVAL, "NULL context");
-    if (mode != ISLF_BARRIER_GRID && mode != ISLF_BARRIER_TEAM) return fail(ISLF_EINVAL, "invalid barrier mode %d", mode);
-    ctx->team_mode = mode == ISLF_BARRIER_TEAM ? 1 : 0;
+    if (mode != ISLF_BARRIER_GRID && mode != ISLF_BARRIER_TEAM && mode != ISLF_BARRIER_AUTO)
+        return fail(ISLF_EINVAL, "invalid barrier mode %d", mode);
+    ctx->team_mode = mode == ISLF_BARRIER_TEAM ? 1 : mode == ISLF_BARRIER_GRID ? 0 : -1;
     ctx->persistent.valid = false;
     ctx->graph_valid = false;
     return ISLF_OK;
@@ -2185,9 +2208,8 @@ extern "C" islf_status islf_set_barriers(islf_ctx *ctx, int32_t mode)
 extern "C" islf_status islf_get_barriers(const islf_ctx *ctx, int32_t *mode)
 {
     if (!ctx || !mode) return fail(ISLF_EINVAL, "NULL argument");
-    // the mode the next persistent launch uses: team barriers need a
-    // workgroup for every live replica
+    // the form the next persistent launch uses
     const int grid = ctx->grid_override ? ctx->grid_override : ctx->persistent_grid;
-    *mode = ctx->team_mode && (int)ctx->live.size() <= grid ? ISLF_BARRIER_TEAM : ISLF_BARRIER_GRID;
+    *mode = use_teams(ctx, grid) ? ISLF_BARRIER_TEAM : ISLF_BARRIER_GRID;
     return ISLF_OK;
 }

@@ -27,7 +27,7 @@ PBC, APBC, GAPBC = 0, 1, 2
 INT8, BITPACK = 0, 1
 INIT_RANDOM, INIT_UP, INIT_DOWN, INIT_HOST = 0, 1, 2, 3
 EXEC_PLAIN, EXEC_BATCHED, EXEC_PERSISTENT = 0, 1, 2
-BARRIER_GRID, BARRIER_TEAM = 0, 1
+BARRIER_GRID, BARRIER_TEAM, BARRIER_AUTO = 0, 1, 2
 
 _STATUS = {EINVAL: "EINVAL", ENOMEM: "ENOMEM", EDEVICE: "EDEVICE", ESTATE: "ESTATE", ERANGE: "ERANGE"}
 
@@ -392,7 +392,7 @@ class Context:
         return t.value, r.value
 
     def set_barriers(self, mode: int):
-        """Barriers of the persistent form: BARRIER_TEAM (per replica) or BARRIER_GRID."""
+        """Barriers of the persistent form: BARRIER_TEAM (per replica), BARRIER_GRID or BARRIER_AUTO."""
         _check(lib().islf_set_barriers(self._h, mode))
 
     def get_barriers(self) -> int:

@@ -188,16 +188,19 @@ def test_phase_timings_are_real_sweeps():
 
 
 @pytest.mark.parametrize("fmt", [islf.INT8, islf.BITPACK])
-@pytest.mark.parametrize("barriers", [islf.BARRIER_TEAM, islf.BARRIER_GRID])
+@pytest.mark.parametrize("barriers", [islf.BARRIER_TEAM, islf.BARRIER_GRID, islf.BARRIER_AUTO])
 def test_persistent_barrier_forms(fmt, barriers):
     # team barriers (each replica's workgroups meet on their own) and grid
     # barriers give the same chains, eager and under graph replay; a grid
-    # smaller than the replica count falls back to grid barriers
+    # smaller than the replica count falls back to grid barriers; the
+    # automatic choice takes teams for int8 spins or 8 and more replicas
     ps = batch_params()
     with islf.Context([islf.Replica(**p) for p in ps], spin_format=fmt, obs_capacity=64,
                       exec_mode=islf.EXEC_PERSISTENT) as ctx:
+        auto = islf.BARRIER_TEAM if fmt == islf.INT8 or len(ps) >= 8 else islf.BARRIER_GRID
+        assert ctx.get_barriers() == auto
         ctx.set_barriers(barriers)
-        assert ctx.get_barriers() == barriers
+        assert ctx.get_barriers() == (auto if barriers == islf.BARRIER_AUTO else barriers)
         ctx.sweep(3)
         ctx.capture(4)
         ctx.replay(2)
