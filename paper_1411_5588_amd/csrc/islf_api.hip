@@ -78,8 +78,8 @@ extern "C" const char *islf_last_error(void) { return g_err.c_str(); }
 // ---------------------------------------------------------------------------
 // tile variants (main tiles, rows 2 .. Ly-2, both formats): a workgroup owns
 // tj columns x ty rows (tj*ty <= 256 threads) and each thread marches through
-// mx x planes; a column is an 8-byte chunk (int8) or a 32-bit word of a
-// sublattice row (bit-packed), and tj is the most even split of a row's
+// mx x planes; a column is an 8-byte column of a sublattice half-row (int8)
+// or a 32-bit word of a sublattice row (bit-packed), and tj is the most even split of a row's
 // columns into pieces of at most tj_max.  Seam-slab tiles (rows Ly-1, 0, 1):
 // np mirror pairs of x planes x nj columns with np*nj <= 128, so that a row
 // stage has at most one task per thread.
@@ -131,7 +131,7 @@ static I8Shape i8_shape(const islf_replica_desc &d, int tile, int fmt = ISLF_SPI
     return s;
 }
 
-// fraction of a plane's thread slots that own a real chunk / word (the x
+// fraction of a plane's thread slots that own a real column / word (the x
 // extent costs nothing: plans cut tiles by x steps)
 static double tile_efficiency(const islf_replica_desc &d, int fmt, int tile)
 {
@@ -321,8 +321,8 @@ static islf_status validate(const islf_replica_desc *d)
     if (!isfinite(d->J) || !isfinite(d->H) || !isfinite(d->h1) || !isfinite(d->hn))
         return fail(ISLF_EINVAL, "J, H, h1, hn must be finite");
     const unsigned long long rows = (unsigned long long)d->Lx * (unsigned long long)d->Ly;
-    const unsigned long long chunks = rows * (unsigned long long)((d->Lz + 7) / 8);
-    if (chunks * 2ull > (1ull << 32))
+    const unsigned long long groups = rows * (unsigned long long)((d->Lz + 7) / 8);   // Philox groups of 8 z
+    if (groups * 2ull > (1ull << 32))
         return fail(ISLF_ERANGE, "lattice %dx%dx%d exceeds the 32-bit Philox group counter", d->Lx, d->Ly, d->Lz);
     if (rows * 16ull * (unsigned long long)((d->Lz + 15) / 16) >= (1ull << 32))
         return fail(ISLF_ERANGE, "lattice %dx%dx%d exceeds 4 GiB of int8 spins", d->Lx, d->Ly, d->Lz);

@@ -173,7 +173,7 @@ __device__ __forceinline__ RepView load_view(const RepDesc *__restrict__ descs, 
 }
 
 // ---------------------------------------------------------------------------
-// int8 format: update the current-phase sites of one 8-byte chunk.
+// int8 format: update the current-phase sites of one 8-byte column.
 // Byte offsets are 32-bit (a replica's spin array is below 4 GiB).
 // ---------------------------------------------------------------------------
 // Loads through the global address space (the spin arrays always live in
@@ -412,7 +412,7 @@ __device__ __forceinline__ void bp_update_word(const RepView &v, int x, int y, i
 // int8 format, main tiles.
 // ---------------------------------------------------------------------------
 // The column a thread of a main tile marches: row y (2 .. Ly-2) and column j
-// (< ncol chunks or words), or false when the thread has none.  A box tile
+// (< ncol columns or words), or false when the thread has none.  A box tile
 // is v.ty rows x v.tj columns from (en.y0, en.j0); a linear tile (v.tj = 0)
 // is the range [en.y0, en.j0) of the plane's main columns in row-major order,
 // one per thread.
