@@ -133,7 +133,9 @@ islf_status islf_get_desc(const islf_ctx *ctx, int32_t rep, islf_replica_desc *o
 
 /* Host <-> device spins, int8 +-1 in the host layout above; n must equal
  * Lx*Ly*Lz.  set_spins also recomputes the initial observables and may only
- * be called before the replica's first sweep (else ESTATE).  Both synchronise.
+ * be called before the replica's first sweep, or on a replica marked failed
+ * by a persistent launch (see islf_sweep), which it restarts at sweep 0
+ * (else ESTATE).  Both synchronise.
  * Errors: EINVAL (n, values other than +-1), ERANGE (rep), ESTATE. */
 islf_status islf_set_spins(islf_ctx *ctx, int32_t rep, const int8_t *host, size_t n);
 islf_status islf_get_spins(islf_ctx *ctx, int32_t rep, int8_t *host, size_t n);
