@@ -940,13 +940,27 @@ __device__ __forceinline__ void slab_stage(const RepView &v, const Entry &en, in
 
 // One slab entry of launch KIND for sweep st.t + s; ends with a workgroup
 // barrier (in the last flush).
+// Stages replica rep's tables in LDS unless they are there already.  key
+// (uniform, kept by the caller across items and, in the persistent kernels,
+// across stages) names what LDS holds: 2 rep + 1 with the pair table, 2 rep
+// without, -1 nothing.  A reload follows a workgroup barrier of the caller
+// (the previous item's flush, or a grid barrier), so no wave still reads the
+// old tables.
+template <bool PAIRS>
+__device__ __forceinline__ void ensure_tables(const RepDesc *__restrict__ descs, int rep, Tables *tb, int &key)
+{
+    if (key == 2 * rep + 1 || (!PAIRS && key == 2 * rep)) return;
+    load_tables<PAIRS>(descs[rep], tb);
+    __syncthreads();
+    key = 2 * rep + (PAIRS ? 1 : 0);
+}
+
 template <int FMT, int KIND, bool COH>
 __device__ __forceinline__ void slab_entry(const RepDesc *__restrict__ descs, const RepState *__restrict__ st,
-                                           const Entry &en, uint32_t s, uint32_t flags, Tables *tb)
+                                           const Entry &en, uint32_t s, uint32_t flags, Tables *tb, int &tb_key)
 {
     const RepView v = load_view(descs, st, en.rep, s);
-    load_tables(descs[en.rep], tb);
-    __syncthreads();
+    ensure_tables<false>(descs, en.rep, tb, tb_key);
     const int slot = blockIdx.x & (kAccSlots - 1);
     Acc a = {0, 0, 0, 0};
     if (KIND == KIND_A) {
@@ -1008,7 +1022,7 @@ __device__ __forceinline__ int plan_block()
 template <int FMT, int KIND, bool COH>
 __device__ __forceinline__ void run_items(const RepDesc *__restrict__ descs, const RepState *__restrict__ st,
                                           const Entry *__restrict__ items, int i0, int i1, uint32_t s,
-                                          uint32_t flags, Tables *tb)
+                                          uint32_t flags, Tables *tb, int &tb_key)
 {
     // a workgroup's slab items come before its main pieces; consecutive main
     // pieces of one replica share the loaded view and tables and one flush
@@ -1017,7 +1031,7 @@ __device__ __forceinline__ void run_items(const RepDesc *__restrict__ descs, con
     for (; i < i1; ++i) {
         const Entry en = items[i];
         if (en.kind != ITEM_SLAB) break;
-        slab_entry<FMT, KIND, COH>(descs, st, en, s, flags, tb);
+        slab_entry<FMT, KIND, COH>(descs, st, en, s, flags, tb, tb_key);
     }
     if (KIND == KIND_F) return;
     const int slot = blockIdx.x & (kAccSlots - 1);
@@ -1029,8 +1043,7 @@ __device__ __forceinline__ void run_items(const RepDesc *__restrict__ descs, con
         if (en.rep != cur) {
             if (cur >= 0) flush_acc(a, v.acc, v.t, slot);   // its barrier frees the tables
             v = load_view(descs, st, en.rep, s);
-            load_tables<FMT == ISLF_SPIN_BITPACK>(descs[en.rep], tb);
-            __syncthreads();
+            ensure_tables<FMT == ISLF_SPIN_BITPACK>(descs, en.rep, tb, tb_key);
             cur = en.rep;
         }
         main_piece<FMT, KIND, COH>(v, en, 0, en.nsteps, tb, a);
@@ -1050,7 +1063,8 @@ __global__ __launch_bounds__(kBlock) void k_sweep(const RepDesc *__restrict__ de
     __shared__ Tables tb;
     if (KIND == KIND_B && (flags & FLAG_FOLD)) fold_waves<false>(descs, st, reps, n_reps, s - 1, 0u);
     const int b = plan_block();
-    run_items<FMT, KIND, false>(descs, st, items, first[b], first[b + 1], s, flags, &tb);
+    int tb_key = -1;
+    run_items<FMT, KIND, false>(descs, st, items, first[b], first[b + 1], s, flags, &tb, tb_key);
 }
 
 // Closes a run of sweeps: folds sweep st.t + s and advances the counters.
@@ -1141,14 +1155,18 @@ __global__ __launch_bounds__(kBlock, 4) void k_persistent(const RepDesc *__restr
     const int b = plan_block();
     const int i0 = first[b], i1 = first[b + 1];
     unsigned long long passed = 0;
+    int tb_key = -1;   // the workgroup's items are the same every stage: tables stay staged
     for (uint32_t s = 0; s < n_sweeps; ++s) {
-        run_items<FMT, KIND_A, true>(descs, st, items, i0, i1, s, s ? FLAG_PREV : 0u, &tb);
+        run_items<FMT, KIND_A, true>(descs, st, items, i0, i1, s, s ? FLAG_PREV : 0u, &tb, tb_key);
         if (!grid_barrier(sync, G, passed)) return;
+        run_items<FMT, KIND_B, true>(descs, st, items, i0, i1, s, 0u, &tb, tb_key);
+        // the record of sweep s-1 is complete since A(s); it is folded after
+        // the workgroup's own B items (off the start of its stage), and before
+        // the barrier that lets A(s+1) add to the same accumulator half
         if (s > 0) fold_waves<true>(descs, st, reps, n_reps, s - 1, 0u);
-        run_items<FMT, KIND_B, true>(descs, st, items, i0, i1, s, 0u, &tb);
         if (!grid_barrier(sync, G, passed)) return;
     }
-    run_items<FMT, KIND_F, true>(descs, st, items, i0, i1, n_sweeps - 1, 0u, &tb);
+    run_items<FMT, KIND_F, true>(descs, st, items, i0, i1, n_sweeps - 1, 0u, &tb, tb_key);
     if (!grid_barrier(sync, G, passed)) return;
     fold_waves<true>(descs, st, reps, n_reps, n_sweeps - 1, n_sweeps);
 }
@@ -1201,14 +1219,16 @@ __global__ __launch_bounds__(kBlock, 4) void k_persistent_teams(const RepDesc *_
     const bool folder = ti.rank == 0 && threadIdx.x < 64;   // wave 0 of rank 0
     const int lane = threadIdx.x & 63;
     unsigned long long passed = 0;
+    int tb_key = -1;   // one replica per workgroup: its tables stay staged
     for (uint32_t s = 0; s < n_sweeps; ++s) {
-        run_items<FMT, KIND_A, true>(descs, st, items, i0, i1, s, s ? FLAG_PREV : 0u, &tb);
+        run_items<FMT, KIND_A, true>(descs, st, items, i0, i1, s, s ? FLAG_PREV : 0u, &tb, tb_key);
         if (!team_barrier(sync, ctr, size, passed)) return;
+        run_items<FMT, KIND_B, true>(descs, st, items, i0, i1, s, 0u, &tb, tb_key);
+        // sweep s-1's record, after the folder's own B items (see k_persistent)
         if (s > 0 && folder) fold_sweep<true>(descs[ti.rep], st[ti.rep], st[ti.rep].t + s - 1, lane);
-        run_items<FMT, KIND_B, true>(descs, st, items, i0, i1, s, 0u, &tb);
         if (!team_barrier(sync, ctr, size, passed)) return;
     }
-    run_items<FMT, KIND_F, true>(descs, st, items, i0, i1, n_sweeps - 1, 0u, &tb);
+    run_items<FMT, KIND_F, true>(descs, st, items, i0, i1, n_sweeps - 1, 0u, &tb, tb_key);
     if (!team_barrier(sync, ctr, size, passed)) return;
     if (folder) {
         fold_sweep<true>(descs[ti.rep], st[ti.rep], st[ti.rep].t + n_sweeps - 1, lane);
