@@ -56,6 +56,14 @@ def test_footprint_and_validation(islf):
     with pytest.raises(islf.IslfError) as e:
         islf.footprint_bytes(islf.Replica(4096, 4096, 4096))
     assert e.value.status == islf.ERANGE
+    # within the 32-bit Philox group counter but at 4 GiB of int8 spins (the
+    # byte offsets and the int8 host-layout staging are 32-bit): refused in
+    # both formats; one plane less fits
+    for fmt in (islf.INT8, islf.BITPACK):
+        with pytest.raises(islf.IslfError) as e:
+            islf.footprint_bytes(islf.Replica(1024, 1024, 4096), fmt)
+        assert e.value.status == islf.ERANGE
+        assert islf.footprint_bytes(islf.Replica(1023, 1024, 4096), fmt) > 0
 
 
 def test_tile_count(islf):
