@@ -302,7 +302,7 @@ islf_status islf_run_graph(islf_ctx *ctx, uint32_t n_replays);
  * whole batch: batched, concurrent groups 1..4 x workgroups per launch (1/2,
  * 1, 3/2 of the default) x share taper (0, 0.1, 0.2); persistent, grid or
  * team barriers x grids of up to one workgroup per CU below the co-residency
- * bound x the same tapers.  The four fastest and the configuration in use
+ * bound x tapers 0, 0.2, 0.4, 0.6.  The four fastest and the configuration in use
  * are timed again (shortest of six runs); a finalist replaces the one in use
  * only if it is 1% faster (islf_get_groups, islf_get_grid, islf_get_taper,
  * islf_get_barriers report the result).  Spins, records and sweep
@@ -317,8 +317,9 @@ islf_status islf_autotune(islf_ctx *ctx, uint32_t sweeps);
  * launch is cut into per-workgroup shares that shrink linearly with the
  * dispatch rank by up to +-taper (later workgroups get less, against the
  * uneven progress of the workgroups resident on one CU).  A negative value
- * restores the built-in one (0 bit-packed and 0.1 int8 batched, 0.1
- * persistent).  Every choice computes the same result; changing it
+ * restores the built-in one (0 bit-packed and 0.1 int8 batched; 0.4
+ * persistent, whose shares step down by dispatch round, one workgroup per CU
+ * per round, since the workgroups resident on a CU progress oldest first).  Every choice computes the same result; changing it
  * invalidates a captured graph.  Errors: EINVAL (NULL, taper >= 1). */
 islf_status islf_set_taper(islf_ctx *ctx, double taper);
 islf_status islf_get_taper(const islf_ctx *ctx, double *taper);

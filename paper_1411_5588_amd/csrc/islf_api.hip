@@ -485,10 +485,15 @@ static double tail_taper(int fmt)
 // a plain launch holds one replica: shorter launches, whose tails weigh more
 constexpr double kPlainTaper = 0.2;
 // the persistent launch has no second round of workgroups to fill a CU
-// whose resident workgroups finish at different times (issue goes oldest
-// first); with its barriers free of cache maintenance a light taper is best
-// in both formats (0.1 measured: 3-7% over 0.4, the best of 0 .. 0.5)
-constexpr double kPersistentTaper = 0.1;
+// whose resident workgroups finish at different times: issue goes oldest
+// first, and per-workgroup timestamps of a launch over three 46M lattices
+// showed the workgroups of the first, second and third dispatch round (one
+// per CU each) finishing equal shares after 19.6, 27 and 36 us.  Its shares
+// therefore step down by dispatch round (grid and team barriers alike);
+// 0.4 measured best or within noise of it (grid barriers: bit-packed 1,869
+// against 1,812 untapered, int8 1,133 against 1,122; teams: int8 1,297
+// against 1,152, bit-packed 1,653 against 1,614; 0 .. 0.7 tried)
+constexpr double kPersistentTaper = 0.4;
 // three concurrent groups: measured as fast as two and faster than four on
 // every batch tried (3 x 160x480x600, 64 x 40x120x120, 96 uneven replicas);
 // four group streams can share one of the process's four hardware queues
@@ -507,7 +512,7 @@ constexpr int kMaxStreamGroups = 16;   // concurrent replica groups of the batch
 // number of workgroups holding slab items.
 static int partition_items(const std::vector<Entry> &slab, const std::vector<Entry> &main, int grid,
                            std::vector<Entry> &items, std::vector<int> &first, double taper, int p0 = 0,
-                           int launch_grid = 0)
+                           int launch_grid = 0, int round = 0)
 {
     auto slab_cost = [](const Entry &e) -> long long {
         const long long tasks = 6ll * e.y0 * e.nsteps;
@@ -544,7 +549,9 @@ static int partition_items(const std::vector<Entry> &slab, const std::vector<Ent
             k = (rg - r8 * (q + 1)) % q;
         }
         const long d = x + 8 * k;
-        const double u = (d + 0.5) / LG;
+        // round > 0: a cooperative grid of `round` workgroups per dispatch
+        // round (one per CU); the taper is a step per round
+        const double u = round > 0 ? ((double)(d / round) + 0.5) / (double)((LG + round - 1) / round) : (d + 0.5) / LG;
         cum[r + 1] = cum[r] + 1.0 + a * (1.0 - 2.0 * u);
     }
     for (int b = 0; b < grid; ++b) {
@@ -578,11 +585,12 @@ static int partition_items(const std::vector<Entry> &slab, const std::vector<Ent
 static islf_status upload_plan(islf_ctx *c, Plan &p, const std::vector<Entry> &items, const std::vector<int> &first);
 
 static islf_status build_plan(islf_ctx *c, Plan &p, const std::vector<Entry> &slab, const std::vector<Entry> &main,
-                              int grid, double taper = -1.0)
+                              int grid, double taper = -1.0, int round = 0)
 {
     std::vector<Entry> items;
     std::vector<int> first;
-    p.slab_grid = partition_items(slab, main, grid, items, first, taper < 0.0 ? tail_taper(c->fmt) : taper);
+    p.slab_grid = partition_items(slab, main, grid, items, first, taper < 0.0 ? tail_taper(c->fmt) : taper, 0, 0,
+                                  round);
     return upload_plan(c, p, items, first);
 }
 
@@ -763,7 +771,8 @@ static islf_status build_team_plan(islf_ctx *c, int grid, double taper)
         std::vector<int> fi;
         // the team's runs are the launch's runs first.size()-1 onwards: their
         // dispatch ranks in the launch set the taper
-        partition_items(c->reps[r].slab, c->reps[r].main, W[i], it, fi, taper, (int)first.size() - 1, grid);
+        partition_items(c->reps[r].slab, c->reps[r].main, W[i], it, fi, taper, (int)first.size() - 1, grid,
+                        c->num_cu);
         const int n = (int)fi.size() - 1;
         const int off = (int)items.size();
         items.insert(items.end(), it.begin(), it.end());
@@ -829,14 +838,12 @@ static islf_status prepare_plans(islf_ctx *c, int exec)
         if (grid > c->persistent_bound)
             return fail(ISLF_ERANGE, "persistent grid %d exceeds the co-residency bound %d of this device", grid,
                         c->persistent_bound);
-        // team plans taper by their launch-wide dispatch ranks too; untapered
-        // was as fast as or faster than 0.1 .. 0.3 on three 46M lattices and
-        // the 64-replica TI batch (bit-packed 1,562 against 1,503 .. 1,521)
+        // team plans taper by their launch-wide dispatch rounds too
         if (use_teams(c, grid))
-            return build_team_plan(c, grid, c->taper_override >= 0.0 ? c->taper_override : 0.0);
+            return build_team_plan(c, grid, c->taper_override >= 0.0 ? c->taper_override : kPersistentTaper);
         const double taper = c->taper_override >= 0.0 ? c->taper_override : kPersistentTaper;
         c->persistent_teams = false;
-        return build_plan(c, c->persistent, S, M, grid, taper);
+        return build_plan(c, c->persistent, S, M, grid, taper, c->num_cu);
     }
     if (exec == ISLF_EXEC_PLAIN) {
         if (c->plain.size() < c->reps.size()) c->plain.resize(c->reps.size());
@@ -1895,9 +1902,10 @@ extern "C" islf_status islf_autotune(islf_ctx *ctx, uint32_t sweeps)
             // up to one workgroup per CU below the bound, like the default grid
             const int per_cu = std::max(1, ctx->persistent_bound / std::max(1, ctx->num_cu));
             const int top = std::max(1, per_cu - 1);
+            // the persistent shares step down by dispatch round: stronger tapers
             for (int team = 0; team <= 1; ++team)
                 for (int k = std::max(1, top - 2); k <= top; ++k)
-                    for (double tp : tapers)
+                    for (double tp : {0.0, 0.2, 0.4, 0.6})
                         trials.push_back(Trial{0, std::min(ctx->num_cu * k, ctx->persistent_bound), tp, team});
         }
         hipEvent_t e0 = nullptr, e1 = nullptr;
@@ -2189,7 +2197,7 @@ extern "C" islf_status islf_get_taper(const islf_ctx *ctx, double *taper)
     if (!ctx || !taper) return fail(ISLF_EINVAL, "NULL argument");
     if (ctx->taper_override >= 0.0) *taper = ctx->taper_override;
     else if (ctx->exec == ISLF_EXEC_PERSISTENT)
-        *taper = use_teams(ctx, ctx->grid_override ? ctx->grid_override : ctx->persistent_grid) ? 0.0 : kPersistentTaper;
+        *taper = kPersistentTaper;
     else *taper = tail_taper(ctx->fmt);
     return ISLF_OK;
 }
