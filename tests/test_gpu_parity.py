@@ -205,3 +205,35 @@ def test_error_paths():
         with pytest.raises(islf.IslfError) as e:
             ctx.set_spins(0, bad)
         assert e.value.status == islf.EINVAL
+
+
+@pytest.mark.parametrize("fmt", FORMATS)
+def test_empty_and_zero_counts(fmt):
+    # zero sweeps and zero replays change nothing; zero-length reads are
+    # refused; a context whose replicas are all retired sweeps nothing and
+    # takes new replicas, which start at sweep 0
+    ps = [config1(Lx=3, Ly=5, Lz=10, replica=0), config1(Lx=2, Ly=4, Lz=6, replica=1)]
+    with islf.Context([rep(p) for p in ps], spin_format=fmt, obs_capacity=16) as ctx:
+        ctx.sweep(0)
+        ctx.sweep(2)
+        ctx.capture(2)
+        ctx.replay(0)
+        ctx.sweep(0)
+        assert [ctx.sweep_count(i) for i in range(2)] == [2, 2]
+        recs = [ctx.measure(i, 0, 2) for i in range(2)]
+        for i, p in enumerate(ps):
+            _, o_rec, o_s = oracle_trajectory(p, 2)
+            assert np.array_equal(recs[i], o_rec)
+            assert np.array_equal(ctx.get_spins(i), o_s)
+        for call in (lambda: ctx.measure(0, 0, 0), lambda: ctx.means(0, 0), lambda: ctx.capture(0)):
+            with pytest.raises(islf.IslfError) as e:
+                call()
+            assert e.value.status == islf.EINVAL
+        ctx.retire(0)
+        ctx.retire(1)
+        ctx.sweep(3)                           # nothing live: nothing to do
+        slot = ctx.add(rep(ps[1]))
+        ctx.sweep(2)
+        assert ctx.sweep_count(slot) == 2
+        _, o_rec, _ = oracle_trajectory(ps[1], 2)
+        assert np.array_equal(ctx.measure(slot, 0, 2), o_rec)
