@@ -430,6 +430,19 @@ __device__ __forceinline__ bool main_column(const RepView &v, const Entry &en, i
     return lin < en.j0;
 }
 
+// The view with its draw key (sweep, replica, key words) read from the first
+// active lane: the values are the same on every lane, and held in scalar
+// registers the Philox round keys cost no vector instructions or registers.
+__device__ __forceinline__ RepView uniform_key(const RepView &v)
+{
+    RepView u = v;
+    u.t = __builtin_amdgcn_readfirstlane(v.t);
+    u.replica = __builtin_amdgcn_readfirstlane(v.replica);
+    u.key0 = __builtin_amdgcn_readfirstlane(v.key0);
+    u.key1 = __builtin_amdgcn_readfirstlane(v.key1);
+    return u;
+}
+
 // Words of one int8 march step, loaded one step ahead of their use.
 struct I8Step {
     uint64_t S, yp, ym, xp;   // own column, rows y+1 / y-1 and plane x+1 at the same column
@@ -466,6 +479,7 @@ __device__ __forceinline__ void i8_march(const RepView &v, const Entry &en, int 
 {
     int y, k;
     if (!main_column(v, en, v.K, y, k)) return;
+    const RepView u = uniform_key(v);
     const int Lx = v.Lx, Ly = v.Ly, K = v.K;
     const int Lzh = v.Lz >> 1;
     const uint32_t RB = v.RB, Hp = v.Hp;
@@ -532,8 +546,8 @@ __device__ __forceinline__ void i8_march(const RepView &v, const Entry &en, int 
         const char *tdc = (const char *)(tb->td + cls * kThrPerClass);
         const char *thc = (const char *)(tb->thr + cls * kThrPerClass);
         uint32_t r0[4], r1[4];
-        philox10<0u>(g, v.t, v.replica, 0u, v.key0, v.key1, r0);
-        philox10<2u>(g, v.t, v.replica, 0u, v.key0, v.key1, r1);
+        philox10<0u>(g, u.t, u.replica, 0u, u.key0, u.key1, r0);
+        philox10<2u>(g, u.t, u.replica, 0u, u.key0, u.key1, r1);
         uint32_t fl = 0, fh = 0;
         int step = 0;
 #pragma unroll
@@ -755,6 +769,7 @@ __device__ __forceinline__ void bp_march(const RepView &v, const Entry &en, int 
 {
     int y, w;
     if (!main_column(v, en, v.Wq, y, w)) return;
+    const RepView u = uniform_key(v);
     const int Lx = v.Lx, Ly = v.Ly, C = v.C, Wq = v.Wq;
     const int nbits = v.Lz >> 1;
     const uint32_t SB = 4u * (uint32_t)Wq;    // bytes of one sublattice row
@@ -788,7 +803,12 @@ __device__ __forceinline__ void bp_march(const RepView &v, const Entry &en, int 
     // flips of up spins, A0..A2 = bit planes of a' = c (up) or 7 - c (down),
     // c = up neighbours; KDM = sum of (6 - k) dm over the surface planes
     int NF = 0, NFU = 0, A0 = 0, A1 = 0, A2 = 0, KDM = 0;
-    for (int x = x0; x < x1; ++x) {
+    // one step at plane x; the surface planes x = 0 and Lx-1 can only be the
+    // first and last step of a march and run apart from the bulk steps (their
+    // own tables, fewer neighbours, the M1 / Mn sums)
+    int x = x0;
+    auto step = [&](auto surface) {
+        constexpr bool SURF = decltype(surface)::value;
         const uint32_t own = own_of(rw, q);
         BpStep nxt;
         const bool more = x + 1 < x1;
@@ -803,11 +823,10 @@ __device__ __forceinline__ void bp_march(const RepView &v, const Entry &en, int 
         const uint32_t b0 = s1 ^ s2, k0 = s1 & s2;
         const uint32_t b1 = c1 ^ c2 ^ k0, b2 = (c1 & c2) | (k0 & (c1 ^ c2));
 
-        // x is uniform across the piece: a scalar branch
-        const bool bulk = x != 0 && x != Lx - 1;
         uint32_t F;
-        if (!NEVER && bulk) F = bp_flips_pairs(S, b2, b1, b0, gq, v, tb);
-        else F = bp_flips<NEVER>(S, b2, b1, b0, gq, v, tb, (x == 0 ? 1 : 0) + (x == Lx - 1 ? 2 : 0));
+        if (SURF) F = bp_flips<NEVER>(S, b2, b1, b0, gq, u, tb, (x == 0 ? 1 : 0) + (x == Lx - 1 ? 2 : 0));
+        else if (NEVER) F = bp_flips<true>(S, b2, b1, b0, gq, u, tb, 0);
+        else F = bp_flips_pairs(S, b2, b1, b0, gq, u, tb);
         F &= vmask;
         st32<COH>(v.spins, own, S ^ F);
         const uint32_t FU = F & S;
@@ -817,7 +836,7 @@ __device__ __forceinline__ void bp_march(const RepView &v, const Entry &en, int 
         A0 += __popc(__builtin_amdgcn_bitop3_b32(F, b0, S, 0x90));
         A1 += __popc(__builtin_amdgcn_bitop3_b32(F, b1, S, 0x90));
         A2 += __popc(__builtin_amdgcn_bitop3_b32(F, b2, S, 0x90));
-        if (!bulk) {
+        if (SURF) {
             const int dm = 2 * __popc(F) - 4 * __popc(FU);
             if (x == 0) a.dM1 += dm;
             if (x == Lx - 1) a.dMn += dm;
@@ -832,7 +851,12 @@ __device__ __forceinline__ void bp_march(const RepView &v, const Entry &en, int 
         gq += gstep;
         gq ^= 1u;
         q ^= 1;
-    }
+        ++x;
+    };
+    if (x0 == 0 && x0 < x1) step(std::true_type{});
+    const int xb1 = min(x1, Lx - 1);
+    while (x < xb1) step(std::false_type{});
+    if (x < x1) step(std::true_type{});
     // a flip of spin s = 2u - 1 with c of its k neighbours up changes B by
     // -2 s (2c - k) = -2 (2a' - k) (up) or -2 (2a' + k - 14) (down); summed
     // with k = 6 - (6 - k): -4 A + 16 NF - 4 NFU + KDM, A = A0 + 2 A1 + 4 A2
