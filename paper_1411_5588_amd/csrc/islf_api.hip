@@ -255,7 +255,8 @@ struct islf_ctx {
     Plan batched, persistent;
     std::vector<Plan> plain;                    // per slot
     // batched form with concurrent replica groups: group g sweeps its
-    // replicas on its own stream (g = 0: the context's stream)
+    // replicas on side_stream[g], a stream the context creates; the
+    // context's stream only forks them and joins them
     int groups_req = 0;                         // 0: automatic
     bool groups_valid = false;
     std::vector<Plan> group_plan;
@@ -668,10 +669,10 @@ static int launch_grid(const islf_ctx *c, int exec)
 
 // Concurrent groups of the batched form: live replicas dealt to the group
 // with the fewest sites so far (largest first), one launch plan per group
-// (2 x resident slots / groups workgroups, so that all groups together keep
-// about two per slot in flight and each group's tail is filled by the
-// others' launches), the groups' live lists on the device, and the side
-// streams and events.
+// (launch_grid: 3/2 x resident slots / groups workgroups, so that all groups
+// together keep about 3/2 per slot in flight and each group's tail is filled
+// by the others' launches), the groups' live lists on the device, and the
+// groups' streams and fork / join events.
 static islf_status prepare_groups(islf_ctx *c)
 {
     islf_status st = sync_tables(c);
@@ -742,11 +743,9 @@ static islf_status build_team_plan(islf_ctx *c, int grid, double taper)
 {
     const int nl = (int)c->live.size();
     std::vector<long long> sites(nl);
-    long long total = 0;
     for (int i = 0; i < nl; ++i) {
         const islf_replica_desc &d = c->reps[c->live[i]].desc;
         sites[i] = (long long)d.Lx * d.Ly * d.Lz;
-        total += sites[i];
     }
     // one workgroup each, then each further workgroup to the team with the
     // most sites per workgroup: the slowest team sets the launch's time
@@ -761,7 +760,6 @@ static islf_status build_team_plan(islf_ctx *c, int grid, double taper)
         heap.back().first = (double)sites[i] / (double)W[i];
         std::push_heap(heap.begin(), heap.end());
     }
-    (void)total;
     std::vector<Entry> items;
     std::vector<int> first(1, 0);
     std::vector<TeamInfo> teams;
@@ -1486,8 +1484,6 @@ extern "C" islf_status islf_energy(const islf_replica_desc *desc, const islf_obs
     return ISLF_OK;
 }
 
-// Host FP64 cumulative trapezoid (Eq. 9 / Eq. 22 over the field, Eq. 19 over
-// beta), left to right.
 // The means of islf_means with the kernel's output in the device's scratch
 // array instead of a staging allocation; the per-replica results are copied
 // to the front of out and moved to their slots from the back (slot ids of
@@ -1534,6 +1530,8 @@ extern "C" islf_status islf_means_noalloc(islf_ctx *ctx, uint64_t first, uint32_
     return ISLF_OK;
 }
 
+// Host FP64 cumulative trapezoid (Eq. 9 / Eq. 22 over the field, Eq. 19 over
+// beta), left to right.
 extern "C" islf_status islf_integrate(const double *h, const double *mean_M1, const double *mean_Mn, int32_t n,
                                       double c1, double cn, double norm, double *cumulative_out)
 {
@@ -1749,16 +1747,16 @@ extern "C" islf_status islf_set_tile(islf_ctx *ctx, int32_t rep, int32_t tile)
     return ISLF_OK;
 }
 
-// Times one tile variant for one size class: the class's replicas sweep
-// `sweeps` times in the batched form over a plan of their own (events on the
-// context stream).  Spins, records and state are restored afterwards by the
-// caller.
 // Timed runs per autotune trial (the shortest counts), and per finalist of
 // the launch-configuration search.
 constexpr int kTrialRuns = 3;
 constexpr int kFinalRuns = 6;
 constexpr int kFinalists = 4;
 
+// Times one tile variant for one size class: the class's replicas sweep
+// `sweeps` times in the batched form over a plan of their own (events on the
+// context stream).  Spins, records and state are restored afterwards by the
+// caller.
 static islf_status time_variant(islf_ctx *c, const std::vector<int> &cls, int tile, uint32_t sweeps, double *ms)
 {
     std::vector<Entry> M, S;
