@@ -137,6 +137,23 @@ def test_films_of_surface_planes(fmt, Lx):
 
 
 @pytest.mark.parametrize("fmt", FORMATS)
+def test_infinite_beta_goes_only_downhill(fmt):
+    # beta = inf (T = 0): every uphill move has threshold 0 and is never
+    # taken, every level or downhill move is always taken; both formats take
+    # their never-accepted path on every plane.  The chain equals the
+    # oracle's, and since the sites of one phase are not neighbours, the
+    # energy never rises from one record to the next.
+    ps = [config1(Lx=Lx, Ly=10, Lz=70, ybc=ybc, beta=float("inf"), H=0.05, h1=0.6, hn=-0.4, replica=20 + Lx)
+          for Lx, ybc in ((1, O.GAPBC), (2, O.APBC), (6, O.PBC), (5, O.GAPBC))]
+    n = 10
+    s0, rec, s1, rc, t = gpu_trajectory(ps, n, fmt=fmt)
+    for i, p in enumerate(ps):
+        assert_same(p, n, s0[i], rec[i], s1[i], rc[i], t[i])
+        E = [O.energy(p["J"], p["H"], p["h1"], p["hn"], r) for r in rec[i]]
+        assert all(E[k + 1] <= E[k] for k in range(n - 1)), (p, E)
+
+
+@pytest.mark.parametrize("fmt", FORMATS)
 def test_host_spins(fmt):
     p = config1(Lx=4, Ly=6, Lz=10, init=islf.INIT_HOST)
     rng = np.random.default_rng(3)
