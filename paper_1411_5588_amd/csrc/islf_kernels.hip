@@ -506,11 +506,13 @@ __device__ __forceinline__ void i8_march(const RepView &v, const Entry &en, int 
     uint64_t O = ld64<COH>(v.spins, own_of(rw, q ^ 1));
     uint64_t xm = x0 > 0 ? ld64<COH>(v.spins, own_of(rw, q) - XB) : 0ull;
     I8Step cur = i8_load_step<COH>(v.spins, own_of(rw, q), edge_of(rw, q), RB, XB, x0 < Lx - 1);
-    // the surface planes x = 0 and Lx-1 can only be the first and last of
-    // the march: their sums are the first and last steps' (no per-step test)
-    int dsum = 0, dfirst = 0, dlast = 0;
-    bool first = true;
-    for (int x = x0; x < x1; ++x) {
+    // the surface planes x = 0 and Lx-1 can only be the first and last step
+    // of a march: they run apart from the bulk steps (their own tables and
+    // M1 / Mn sums), the bulk steps use the bulk class's table
+    int dsum = 0, dsurf1 = 0, dsurfn = 0;
+    int x = x0;
+    auto step = [&](auto surface) {
+        constexpr bool SURF = decltype(surface)::value;
         const uint32_t own = own_of(rw, q);
         I8Step nxt;
         const bool more = x + 1 < x1;
@@ -542,7 +544,7 @@ __device__ __forceinline__ void i8_march(const RepView &v, const Entry &en, int 
         // per byte 8 (8u + cnt): the entry's byte offset in its class's table
         const uint32_t il = (cl + (sl << 3)) << 3;
         const uint32_t ih = (ch + (sh << 3)) << 3;
-        const int cls = (x == 0 ? 1 : 0) + (x == Lx - 1 ? 2 : 0);
+        const int cls = SURF ? (x == 0 ? 1 : 0) + (x == Lx - 1 ? 2 : 0) : 0;
         const char *tdc = (const char *)(tb->td + cls * kThrPerClass);
         const char *thc = (const char *)(tb->thr + cls * kThrPerClass);
         uint32_t r0[4], r1[4];
@@ -566,9 +568,10 @@ __device__ __forceinline__ void i8_march(const RepView &v, const Entry &en, int 
         }
         st64<COH>(v.spins, own, cur.S ^ (((uint64_t)fh << 32) | fl));
         dsum += step;
-        if (first) dfirst = step;
-        first = false;
-        dlast = step;
+        if (SURF) {
+            if (x == 0) dsurf1 = step;
+            if (x == Lx - 1) dsurfn = step;
+        }
         // the next plane: its x-1 word is this plane's other sublattice, its
         // other-sublattice word is this plane's x+1 word
         xm = O;
@@ -578,15 +581,19 @@ __device__ __forceinline__ void i8_march(const RepView &v, const Entry &en, int 
         g += gstep;
         g ^= 1u;
         q ^= 1;
-    }
+        ++x;
+    };
+    if (x0 == 0 && x0 < x1) step(std::true_type{});
+    const int xb1 = min(x1, Lx - 1);
+    while (x < xb1) step(std::false_type{});
+    if (x < x1) step(std::true_type{});
     // packed sums: dB in the low 16 bits (|sum| < 2^15 for <= kMaxMarch planes of 8 sites)
     const int dB = (int)(int16_t)(dsum & 0xFFFF), dM = (dsum - dB) >> 16;
     a.dB += dB;
     a.dM += dM;
-    const int d1 = x0 == 0 ? dfirst : 0, dn = x1 == Lx ? dlast : 0;
-    const int dB1 = (int)(int16_t)(d1 & 0xFFFF), dBn = (int)(int16_t)(dn & 0xFFFF);
-    a.dM1 += (d1 - dB1) >> 16;
-    a.dMn += (dn - dBn) >> 16;
+    const int dB1 = (int)(int16_t)(dsurf1 & 0xFFFF), dBn = (int)(int16_t)(dsurfn & 0xFFFF);
+    a.dM1 += (dsurf1 - dB1) >> 16;
+    a.dMn += (dsurfn - dBn) >> 16;
 }
 
 // Spreads the low 8 bits of x to bits 0, 4, 8, ..., 28 (one site per nibble).
@@ -1166,8 +1173,13 @@ __device__ bool grid_barrier(GridSync *sync, unsigned long long nblocks, unsigne
     return ok != 0;
 }
 
+// Occupancy floor of the persistent kernels: four workgroups per CU, five
+// for int8 (whose march fits the registers of five without spilling, so its
+// co-residency bound leaves room for a default grid of four per CU).
+constexpr int persistent_min_blocks(int fmt) { return fmt == ISLF_SPIN_INT8 ? 5 : 4; }
+
 template <int FMT>
-__global__ __launch_bounds__(kBlock, 4) void k_persistent(const RepDesc *__restrict__ descs,
+__global__ __launch_bounds__(kBlock, persistent_min_blocks(FMT)) void k_persistent(const RepDesc *__restrict__ descs,
                                                        RepState *__restrict__ st,
                                                        const Entry *__restrict__ items,
                                                        const int *__restrict__ first,
@@ -1226,7 +1238,7 @@ __device__ bool team_barrier(GridSync *sync, SyncLine *team, unsigned long long 
 // at the end, advances its sweep counter.  A barrier that gives up (bounded
 // wait, or a raised error word) ends every workgroup at its next barrier.
 template <int FMT>
-__global__ __launch_bounds__(kBlock, 4) void k_persistent_teams(const RepDesc *__restrict__ descs,
+__global__ __launch_bounds__(kBlock, persistent_min_blocks(FMT)) void k_persistent_teams(const RepDesc *__restrict__ descs,
                                                                 RepState *__restrict__ st,
                                                                 const Entry *__restrict__ items,
                                                                 const int *__restrict__ first,
