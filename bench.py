@@ -271,12 +271,14 @@ def committed_traffic(fmt):
 def committed_valu(fmt):
     """Counter-based VALU figures of the same launches: the share of the
     dispatch's SIMD issue slots that issued a VALU instruction
-    (SQ_ACTIVE_INST_VALU over GRBM_GUI_ACTIVE cycles) and VALU lane-ops per
-    update."""
+    (SQ_ACTIVE_INST_VALU over GRBM_GUI_ACTIVE cycles), the issue time of a
+    launch's VALU instructions (quad-cycles over the 1024 SIMDs at 2.4 GHz)
+    and VALU lane-ops per update."""
     f = committed_figure(PROFILE_VALU, f"valu_issue_frac[{fmt}]")
     if f is None:
         return None
-    return {"issue_frac": f, "lane_ops_per_update": committed_figure(PROFILE_VALU, f"valu_lane_ops_per_update[{fmt}]"),
+    return {"issue_frac": f, "issue_us_per_launch": committed_figure(PROFILE_VALU, f"valu_issue_us_per_launch[{fmt}]"),
+            "lane_ops_per_update": committed_figure(PROFILE_VALU, f"valu_lane_ops_per_update[{fmt}]"),
             "source": os.path.relpath(PROFILE_VALU, ROOT)}
 
 
@@ -570,6 +572,11 @@ def main():
                                    "unit": f"wave of {grouped['groups']} concurrent group dispatches of "
                                            f"{grouped['grid']} workgroups, half a sweep of every replica"}
         out["valu"] = committed_valu(fmt)
+        if grouped is not None and out["valu"] and out["valu"].get("issue_us_per_launch"):
+            # the same half sweep's VALU issue time over the grouped wave: the
+            # share of the wave the SIMDs spend issuing VALU instructions
+            out["grouped_wave"]["valu_issue_frac"] = round(
+                out["valu"]["issue_us_per_launch"] / (out["grouped_wave"]["wave_ms"] * 1e3), 3)
         out["limiter"] = "VALU issue: Philox4x32-10 costs 5 64-bit products and 5 xors per update"
         return out
 
